@@ -1,0 +1,270 @@
+"""Throughput of the semi-explicit eddy-current step on one MI355X.
+
+Workload: the nonlinear 48^3-cell FIT grid (unit cube, PEC walls) with a
+16^3-cell Brauer iron conductor (sigma = 2e6 S/m, nu = 3.8 exp(2.17 B^2) +
+396.2), a coil current ramped linearly over 1000 steps, dt = half the
+explicit-Euler stability bound (eq. 8, power method on the GPU), PCG to a
+relative residual of 1e-8.  Each timed step is one explicit Euler step of
+eqs. (6)-(7): two pseudo-inverse solves (source and coupling sequences),
+their start vectors and history updates, and the conducting-region update.
+
+The headline value is steps/s with SPE start vectors (window m = 8) replayed
+from a captured HIP graph; ZERO (plain zero-start PCG), PREV and POD
+(20 snapshots, at most 10 modes) run the same steps for comparison.
+Inputs are synthetic (seeded geometry; no benchmark data).
+
+Usage: python bench.py [--steps K] [--warmup W] [--methods spe,pod,prev,zero]
+                       [--cpu-steps S] [--no-cpu] [--no-probe]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Euler steps/sec at rel. residual 1e-8; PCG iters/step; SpMV HBM GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1611_06721_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def method_opts(ec, name, budget, rtol):
+    if name == "spe":
+        return ec.step_opts(ec.SV_SPE, window=8, pod_kmax=8, rtol=rtol, maxit=budget)
+    if name == "pod":
+        return ec.step_opts(ec.SV_POD, window=20, pod_kmax=10, pod_eps=1e-4, rtol=rtol,
+                            maxit=budget)
+    if name == "prev":
+        return ec.step_opts(ec.SV_PREV, window=1, rtol=rtol, maxit=budget)
+    return ec.step_opts(ec.SV_ZERO, window=1, rtol=rtol, maxit=budget)
+
+
+def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
+    """Eager warm-up (sizes the per-solve iteration budget of the graph), then
+    `steps` graph replays from rest, timed with events on the bound stream."""
+    A = G.zeros()
+    G.set_state(A, rtol=rtol)
+    info = G.info(2 * warmup)
+    G.run(A, 0, warmup, dt, method_opts(ec, name, 100000, rtol), info=info)
+    its = ec.info_array(info)["iters"]
+    budget = int(max(its.max() * 1.5, its.max() + 16))
+    for attempt in range(3):
+        A.zero_()
+        G.set_state(A, rtol=rtol)
+        G.set_step(0)
+        G.counters_reset()
+        graph = G.graph_capture(A, dt, method_opts(ec, name, budget, rtol))
+        torch.cuda.synchronize()
+        s = G.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            graph.launch_raw()
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        c = G.counters()
+        del graph
+        if c["worst_status"] == 0 and c["steps"] == steps:
+            break
+        log(f"[bench] {name}: budget {budget} insufficient (status {c['worst_status']}), retry")
+        budget *= 2
+    else:
+        raise RuntimeError(f"{name}: solves did not converge within the graph budget")
+    return {
+        "steps_per_s": steps / (ms * 1e-3),
+        "ms_per_step": ms / steps,
+        "iters_per_step": (c["iters_src"] + c["iters_cpl"]) / steps,
+        "iters_src_per_step": c["iters_src"] / steps,
+        "iters_cpl_per_step": c["iters_cpl"] / steps,
+        "graph_iteration_budget": budget,
+        "final_state_norm": float(A.norm().item()),
+    }, A
+
+
+def time_cg_iteration(ec, torch, G, reps=400):
+    """Average duration of one PCG iteration kernel (FP64): a solve that runs
+    exactly `reps` iterations, between events on the bound stream."""
+    import numpy as np
+    b = torch.randn(G.n_pad, dtype=torch.float64, device=G.device)
+    b = G.apply(ec.OP_KN, b)             # a consistent right-hand side
+    x = G.zeros()
+    for r in (reps, reps):               # the first run sets the chunk hint to reps
+        s = G.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        G.solve(b, x=x, method=ec.SV_ZERO, rtol=1e-300, maxit=r)
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+    return 1e3 * ms / reps
+
+
+def time_spmv(ec, torch, G, reps=50):
+    x = torch.randn(G.n_pad, dtype=torch.float64, device=G.device)
+    y = G.zeros()
+    G.apply(ec.OP_KN, x, out=y)
+    s = G.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        G.apply(ec.OP_KN, x, out=y)
+    e1.record(s)
+    e1.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / reps
+
+
+def traffic_record(kernel, workload):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled by a
+    copy kernel) if recorded for the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    ent = rec.get(f"{kernel}@{workload}")
+    if not ent or ent.get("sources") != kernel_sources_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(steps, dt):
+    """The oracle (plain FP64 C, zero-start CG) on the host cores: the first
+    `steps` steps of the same workload."""
+    import oracle
+    import synth
+    threads = min(os.cpu_count() or 1, 16)
+    oracle.set_threads(threads)
+    O = oracle.Problem(synth.nonlinear(48))
+    t = time.time()
+    O.run(dt, steps, rtol=1e-8)
+    el = time.time() - t
+    return {"value": steps / el, "unit": "steps/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"steps 1..{steps} of the 48^3 nonlinear run, zero-start CG, "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--methods", default="spe,pod,prev,zero")
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1611_06721_amd as ec
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    rtol = 1e-8
+    wl = synth.nonlinear(48)
+    G = ec.Problem(wl, window_cap=20)
+    lam = G.cfl(iters=60, rtol=1e-10)
+    dt = 0.5 * 2.0 / lam
+    log(f"[bench] 48^3 nonlinear: n_pad {G.n_pad}, lambda_max {lam:.6g}, dt {dt:.4g}")
+
+    results = {}
+    for name in args.methods.split(","):
+        log(f"[bench] method {name}: warmup {args.warmup}, {args.steps} steps")
+        r, _ = run_method(ec, torch, G, name, dt, args.steps, args.warmup, rtol)
+        results[name] = r
+        log(f"[bench] {name}: {r['steps_per_s']:.1f} steps/s, {r['iters_per_step']:.2f} iters/step")
+    head = "spe" if "spe" in results else next(iter(results))
+
+    # dominant kernel: the PCG iteration (single-reduction Jacobi-PCG, FP64)
+    N = 48
+    n_alg = 3 * N * (N + 1) ** 2                 # padded edge elements (algorithmic unit)
+    cg_us = time_cg_iteration(ec, torch, G)
+    cg_bytes = 80.0 * n_alg
+    achieved = cg_bytes / (cg_us * 1e-6) / 1e9
+    traffic = traffic_record("k_cg_iter", "48^3")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "kernel": "k_cg_iter<double> (one PCG iteration)",
+                "avg_us": round(cg_us, 3), "bytes_per_launch": cg_bytes}
+    spmv_us = time_spmv(ec, torch, G)
+    extra = {"spmv_48": {"avg_us_incl_mask": round(spmv_us, 3)}}
+    del G
+    torch.cuda.empty_cache()
+
+    if not args.no_probe:
+        # HBM-resident sizes: the working set exceeds the 256 MB Infinity Cache
+        for Np in (128, 256):
+            Gp = ec.Problem(synth.nonlinear(Np), window_cap=1)
+            nn = 3 * Np * (Np + 1) ** 2
+            us = time_cg_iteration(ec, torch, Gp, reps=60 if Np == 256 else 200)
+            extra[f"cg_iter_{Np}"] = {"avg_us": round(us, 2),
+                                      "achieved_GBs": round(80.0 * nn / (us * 1e-6) / 1e9, 1),
+                                      "frac": round(80.0 * nn / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+            del Gp
+            torch.cuda.empty_cache()
+            log(f"[bench] probe {Np}^3: cg iteration {us:.1f} us")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_steps, dt)
+        log(f"[bench] cpu oracle: {cpu['value']:.3f} steps/s on {cpu['cores']} threads")
+
+    r = results[head]
+    line = {
+        "metric": METRIC,
+        "value": round(r["steps_per_s"], 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "nonlinear 48^3 FIT cube, Brauer iron 16^3, coil ramp 1000 "
+                               "steps, dt = 0.5 x CFL bound, rtol 1e-8",
+                   "start_vector": {"spe": "SPE window 8", "pod": "POD 20 snapshots <=10 modes",
+                                    "prev": "previous solution", "zero": "zero"}[head],
+                   "graph": True},
+        "iters_per_step": round(r["iters_per_step"], 3),
+        "spmv_hbm_gbs": round(achieved, 2),
+        "methods": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                        for kk, vv in v.items()} for k, v in results.items()},
+        "roofline": roofline,
+        "probe": extra,
+        "cpu_baseline": cpu,
+    }
+    if "zero" in results and head != "zero":
+        line["speedup_vs_zero_start"] = round(r["steps_per_s"] / results["zero"]["steps_per_s"], 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

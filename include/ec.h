@@ -1,0 +1,228 @@
+/*
+ * ec.h -- C-ABI of the MI355X (gfx950) library for the semi-explicit
+ * eddy-current scheme of Dutine, Clemens and Schoeps, "Multiple right-hand
+ * side techniques in semi-explicit time integration methods for transient
+ * eddy current problems" (Secs. II-III).
+ *
+ * The magnetic vector potential is discretised on a staggered Cartesian
+ * (FIT) grid with edge unknowns.  The dofs split into conducting (a_c) and
+ * nonconducting (a_n) edges, giving the DAE of eq. (3).  The generalised
+ * Schur complement (eq. 4) turns it into the ODE (5a), integrated by explicit
+ * Euler (eqs. 6, 7).  Every step needs pseudo-inverse solves with the
+ * nonconducting curl-curl matrix K_n (eq. 9), done by Jacobi-preconditioned
+ * CG started from SPE (eq. 10) or POD (eqs. 11-14) vectors.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status: every call returns EC_OK (0) or a negative EC_ERR_* code; the
+ *   message of the last failure is ec_last_error(h).  No C++ exception
+ *   crosses this boundary.
+ * Edge arrays ("padded" layout): one array of 3*S elements, S =
+ *   (nx+1)(ny+1)(nz+1).  Block c (0 x, 1 y, 2 z) holds the edges of direction
+ *   c; inside a block the edge anchored at node (i,j,k) is at
+ *   (k*(ny+1)+j)*(nx+1)+i.  Slots with i = nx (x), j = ny (y), k = nz (z)
+ *   are padding.  Entries on Dirichlet (boundary-tangential) edges and padding
+ *   must be zero on input and are zero on output.  The state array A holds
+ *   a_c on conducting edges and a_n on nonconducting ones.
+ * Memory: pointers named "dev" or documented as device pointers are HIP
+ *   device memory owned by the caller, 16-byte aligned.  Host pointers are
+ *   read during the call only.  The library never allocates device memory:
+ *   all of its scratch lives in the caller's workspace (ec_bind).
+ * Streams: after ec_bind every device call is enqueued asynchronously on the
+ *   bound HIP stream, except where a call says it synchronises.  Handles are
+ *   not thread-safe.
+ */
+#ifndef EC_H
+#define EC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ec_problem *ec_handle;
+
+enum {
+    EC_OK = 0,
+    EC_ERR_ARG = -1,            /* invalid argument or size */
+    EC_ERR_HIP = -2,            /* HIP runtime failure */
+    EC_ERR_NOT_CONVERGED = -3,  /* PCG reached maxit */
+    EC_ERR_BREAKDOWN = -4,      /* p^T K_n p <= 0 with r != 0 */
+    EC_ERR_CFL = -5,            /* dt above the stability bound (eq. 8) */
+    EC_ERR_NONFINITE = -6,      /* NaN or Inf in a solve or in the state */
+    EC_ERR_STATE = -7,          /* call out of order (not bound, ...) */
+    EC_ERR_SINGULAR_PROJ = -8   /* projected SPE/POD matrix not SPD: zero start used */
+};
+
+enum { EC_WF_DC = 0, EC_WF_SIN = 1, EC_WF_RAMP = 2, EC_WF_EXP = 3 };
+enum { EC_SEQ_SRC = 0, EC_SEQ_CPL = 1, EC_SEQ_ADJ = 2, EC_SEQ_USER = 3, EC_NSEQ = 4 };
+enum { EC_SV_ZERO = 0, EC_SV_PREV = 1, EC_SV_SPE = 2, EC_SV_POD = 3 };
+enum { EC_PREC_FP64 = 0, EC_PREC_FP32_REFINED = 1 };
+enum { EC_OP_KN = 0, EC_OP_KCN_T = 1, EC_OP_KC_KCN = 2 };
+
+#define EC_MAX_WINDOW 20
+
+/* Uniform grid of n[0] x n[1] x n[2] cells on a box of side lengths len [m]. */
+typedef struct { int32_t n[3]; double len[3]; } ec_grid;
+
+/* Conducting material: sigma > 0 [S/m]; reluctivity nu(B) = k1 exp(k2 |B|^2)
+ * + k3 [m/H] (the nonlinear nu of eq. 1; k1 = 0 gives the constant k3). */
+typedef struct { double sigma, k1, k2, k3; } ec_material;
+
+/* cell_mat (host, nx*ny*nz bytes, cell (i,j,k) at (k*ny+j)*nx+i): 0 marks a
+ * nonconducting cell of reluctivity nu0, m >= 1 selects mats[m-1]. */
+typedef struct {
+    const uint8_t *cell_mat;
+    const ec_material *mats;
+    int32_t n_mats;
+    double nu0;
+} ec_materials;
+
+/* Source j_S = X_S i_S(t) (eq. 1): edge_current is X_S as a host padded edge
+ * array [A per unit i_S], nonzero on nonconducting edges only and discretely
+ * divergence free.  i_S(t_m), t_m = m dt: DC amp; SIN amp sin(2 pi freq t);
+ * RAMP amp min(1, m/ramp_steps); EXP amp (1 - exp(-t/tau)) (Sec. IV). */
+typedef struct {
+    const double *edge_current;
+    int32_t waveform;
+    double amp, freq, tau;
+    int64_t ramp_steps;
+} ec_source;
+
+/* PCG options.  Stop when ||b - K_n x||_2 <= rtol ||b||_2 (recursive
+ * residual).  FP32_REFINED: FP32 inner PCG to inner_rtol inside an FP64
+ * residual-refinement loop of at most outer_max passes. */
+typedef struct {
+    double rtol;
+    int32_t maxit;
+    int32_t precision;
+    double inner_rtol;
+    int32_t inner_maxit;
+    int32_t outer_max;
+} ec_solve_opts;
+
+/* Record written to device memory by every solve. */
+typedef struct {
+    int32_t iters;        /* PCG iterations (inner ones summed for FP32_REFINED) */
+    int32_t outer_iters;  /* refinement passes (FP32_REFINED), else 0 */
+    int32_t status;       /* EC_OK or EC_ERR_* */
+    int32_t basis_cols;   /* SPE basis / POD modes used by the start vector */
+    double rel_res;       /* final ||r|| / ||b|| */
+    double b_norm;        /* ||b|| */
+    double pod_info;      /* eq. (13) value of the POD truncation (else 1) */
+    double r0_rel;        /* ||r_0|| / ||b|| of the start vector */
+} ec_solve_info;
+
+/* Step options: start-vector method and its window (SPE: last `window`
+ * accepted solutions; POD: `window` snapshots, at most pod_kmax modes with
+ * sigma_i >= pod_eps sigma_1). */
+typedef struct {
+    int32_t start_method;
+    int32_t window;
+    int32_t pod_kmax;
+    double pod_eps;
+    ec_solve_opts solve;
+} ec_step_opts;
+
+/* Create a problem (host only): validates the descriptors, builds the edge
+ * classes (Dirichlet / conducting / nonconducting), M_sigma, the reluctivity
+ * tables and checks that X_S lies on nonconducting edges and has zero
+ * discrete divergence (G^T X_S = 0, needed for a consistent right-hand side
+ * of the singular K_n, Sec. II).  EC_ERR_ARG on any violation.  *out = NULL
+ * on failure; ec_last_error(NULL) then holds the message. */
+int32_t ec_create(const ec_grid *grid, const ec_materials *mat,
+                  const ec_source *src, ec_handle *out);
+int32_t ec_destroy(ec_handle h);
+
+/* Sizes: padded edge-array length, conducting and nonconducting edge counts
+ * and the workspace bytes needed for start-vector windows of up to
+ * `window_cap` columns (1..EC_MAX_WINDOW). */
+int32_t ec_sizes(ec_handle h, int32_t window_cap, int64_t *n_padded, int64_t *n_c,
+                 int64_t *n_n, int64_t *workspace_bytes);
+
+/* Bind a HIP stream and a caller-owned device workspace of at least
+ * ec_sizes(...) bytes (256-byte aligned).  Uploads the tables and zeroes the
+ * state (a = 0, empty histories); synchronises the stream. */
+int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64_t bytes,
+                int32_t window_cap);
+
+/* y = op(x) on device padded arrays (y must not alias x):
+ *   EC_OP_KN      y = K_n x            (x read on nonconducting edges)
+ *   EC_OP_KCN_T   y = K_cn^T x_c       (x read on conducting edges), eq. (7)
+ *   EC_OP_KC_KCN  y = K_c(x_c) x_c + K_cn x_n on conducting edges, with the
+ *                 reluctivity evaluated at x (eq. 3, first block row). */
+int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y);
+
+/* Sequence histories (eq. 9: one history per right-hand-side sequence).
+ * reset empties it; push appends a solution x (device padded array). */
+int32_t ec_history_reset(ec_handle h, int32_t seq);
+int32_t ec_history_push(ec_handle h, int32_t seq, int32_t method, int32_t window,
+                        const double *x);
+
+/* x0 from the history of `seq`: SPE (eq. 10) or POD (eq. 14) Galerkin
+ * projection x0 = U (U^T K_n U)^{-1} U^T b; an empty history gives x0 = 0.
+ * info (device, may be NULL) receives basis_cols, pod_info and r0_rel. */
+int32_t ec_start_vector(ec_handle h, int32_t seq, int32_t method, int32_t window,
+                        int32_t pod_kmax, double pod_eps, const double *b, double *x0,
+                        ec_solve_info *dev_info);
+
+/* K_n x = b by Jacobi-PCG (eq. 9).  method: ZERO (x0 = 0), PREV (x holds the
+ * start), SPE/POD (start from the history, then push the solution).
+ * dev_info (device, may be NULL) receives the record.  Asynchronous: a
+ * non-converged solve is reported in the record, not in the return value. */
+int32_t ec_solve(ec_handle h, int32_t seq, int32_t method, int32_t window,
+                 const double *b, double *x, const ec_solve_opts *opts,
+                 ec_solve_info *dev_info);
+
+/* Replace the state: A (device padded) becomes a^{m-1}; recomputes
+ * K_n^+ K_cn^T a_c (zero-start solve at opts->rtol) and empties histories.
+ * Synchronises. */
+int32_t ec_set_state(ec_handle h, const double *A, const ec_solve_opts *opts);
+
+/* One explicit Euler step m (eqs. 6 and 7, with the sign of eq. 5a):
+ *   s_j = K_n^+ j^m;  g = K_c(a_c) a_c + K_cn (s_j - s_c);
+ *   a_c^m = a_c^{m-1} - dt M_c^{-1} g;  s_c = K_n^+ K_cn^T a_c^m;
+ *   a_n^m = s_j - s_c.
+ * A (device) holds a^{m-1} on entry and a^m on exit; it must be the array of
+ * the previous step (or of ec_set_state).  m < 0 takes the step index from
+ * the device counter (advanced by every step).  dev_info (device, may be
+ * NULL) receives two records: the source and the coupling solve. */
+int32_t ec_step(ec_handle h, int64_t m, double dt, double *A, const ec_step_opts *opts,
+                ec_solve_info *dev_info);
+
+/* nsteps steps m0+1..m0+nsteps without host synchronisation; dev_info, if
+ * not NULL, receives 2*nsteps records. */
+int32_t ec_run(ec_handle h, int64_t m0, int64_t nsteps, double dt, double *A,
+               const ec_step_opts *opts, ec_solve_info *dev_info);
+
+/* Set the device step counter to m (the last completed step): the next
+ * step with a negative m, or the next replay of a captured step, is m+1. */
+int32_t ec_set_step(ec_handle h, int64_t m);
+
+/* Device-side totals since bind or the last reset: solves, PCG iterations
+ * per sequence, worst status.  Synchronises. */
+int32_t ec_counters(ec_handle h, int64_t *n_steps, int64_t *iters_src, int64_t *iters_cpl,
+                    int64_t *iters_adj, int32_t *worst_status);
+int32_t ec_counters_reset(ec_handle h);
+
+/* Largest eigenvalue of M_c^{-1} K_S(a_c) (eq. 8) by the power method with
+ * `power_iters` iterations (each one K_n^+ solve), reluctivity frozen at A.
+ * Synchronises; result in *lambda_max (host). */
+int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, double rtol,
+               double *lambda_max);
+
+/* HIP graph of one step (device step counter, fixed dt and opts) captured on
+ * the bound stream; launch replays it on `hip_stream`. */
+int32_t ec_graph_capture_step(ec_handle h, double dt, double *A, const ec_step_opts *opts,
+                              ec_solve_info *dev_info, void **graph_exec);
+int32_t ec_graph_launch(void *graph_exec, void *hip_stream);
+int32_t ec_graph_destroy(void *graph_exec);
+
+/* Message of the last failure on h (or of the last ec_create if h = NULL). */
+const char *ec_last_error(ec_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -119,8 +119,12 @@ class Problem:
         self.D = self.cls == CLS_D
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().or_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.or_destroy(h)
+            except Exception:
+                pass
             self._h = None
 
     # -- operators ---------------------------------------------------------

@@ -1,0 +1,716 @@
+// ec_basis.hip -- start vectors of Sec. III on gfx950.
+//
+// SPE (eq. 10): per right-hand-side sequence an orthogonal basis q of the
+// span of the last m accepted solutions, kept with its K_n products (the
+// cascaded reuse of the paper: only a new column needs an SpMV), and
+// x0 = q (q^T K_n q)^{-1} q^T b.  New solutions are orthogonalised by two
+// classical Gram-Schmidt passes; the oldest solution leaves the window by a
+// Givens downdate of the window's triangular coordinates, which rotates the
+// basis (and its K_n products) in place.
+// POD (eqs. 11-14): a ring of N_POD snapshots X with K_n X; the snapshot Gram
+// matrix X^T X = V Sigma^2 V^T gives the left singular vectors u_j =
+// X v_j / sigma_j (method of snapshots), truncated by sigma_j >= eps sigma_1
+// and at most kmax modes; eq. (13) is reported; x0 from eq. (14).
+//
+// The tall-skinny products run on the FP64 matrix cores and leave one row of
+// partial sums per block; a one-block kernel reduces the rows in a fixed
+// order and performs the small dense step of the sequence (OP_* codes).
+#include <math.h>
+
+#include "ec_device.h"
+
+namespace ec {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int K = kMaxWin;
+constexpr int KC = EC_MAX_WINDOW + 1;     // columns a basis can hold
+
+// ------------------------------------------------ small dense primitives
+// All threads of the block call these (uniform barriers); serial parts run
+// on thread 0, parallel loops stride over the block.
+
+// Cholesky solve H y = g (n x n, leading dimension K); false if H is not
+// numerically positive definite.
+__device__ bool chol_solve(const double *H, double *L, double *y, const double *gv, int n)
+{
+    __shared__ int s_bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) s_bad = 0;
+    for (int t = tid; t < n * n; t += nt) {
+        const int r = t / n, c = t - r * n;
+        L[r * K + c] = H[r * K + c];
+    }
+    __syncthreads();
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(L[i * K + i]));
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            const double d = L[j * K + j];
+            if (!(d > 1e-14 * dmax)) s_bad = 1;
+            L[j * K + j] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double ljj = L[j * K + j];
+        for (int i = j + 1 + tid; i < n; i += nt) L[i * K + j] /= ljj;
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int t = tid; t < m * m; t += nt) {
+            const int r = j + 1 + t / m, c = j + 1 + t % m;
+            if (c <= r) L[r * K + c] -= L[r * K + j] * L[c * K + j];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int i = 0; i < n; ++i) {
+            double s = gv[i];
+            for (int j = 0; j < i; ++j) s -= L[i * K + j] * y[j];
+            y[i] = s / L[i * K + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int j = i + 1; j < n; ++j) s -= L[j * K + i] * y[j];
+            y[i] = s / L[i * K + i];
+        }
+    }
+    __syncthreads();
+    return s_bad == 0;
+}
+
+// Symmetric eigen-decomposition of A (n x n) by cyclic Jacobi with
+// round-robin pairing (n/2 independent rotations per round), starting from
+// the orthogonal V given; A ends diagonal, the columns of V are eigenvectors.
+__device__ void jacobi_eig(double *A, double *V, int n)
+{
+    __shared__ double cs[K / 2 + 1][2];
+    __shared__ int pr[K / 2 + 1][2];
+    __shared__ int s_done;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int m = (n + 1) & ~1;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (tid == 0) {
+            double off = 0.0, dia = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    const double x = A[i * K + j] * A[i * K + j];
+                    if (i == j) dia += x; else off += x;
+                }
+            s_done = off <= 1e-30 * dia;
+        }
+        __syncthreads();
+        if (s_done) break;
+        for (int round = 0; round < m - 1; ++round) {
+            if (tid < m / 2) {
+                auto slot = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + round) % (m - 1); };
+                int p = slot(tid), q = slot(m - 1 - tid);
+                if (p > q) { const int t = p; p = q; q = t; }
+                pr[tid][0] = p;
+                pr[tid][1] = q;
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[p * K + q];
+                    if (apq != 0.0) {
+                        const double th = (A[q * K + q] - A[p * K + p]) / (2.0 * apq);
+                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                    }
+                }
+                cs[tid][0] = c;
+                cs[tid][1] = s;
+            }
+            __syncthreads();
+            for (int t = tid; t < (m / 2) * n; t += nt) {       // A <- A J, V <- V J
+                const int pi = t / n, r = t - pi * n;
+                const int p = pr[pi][0], q = pr[pi][1];
+                if (q >= n) continue;
+                const double c = cs[pi][0], s = cs[pi][1];
+                const double ap = A[r * K + p], aq = A[r * K + q];
+                A[r * K + p] = c * ap - s * aq;
+                A[r * K + q] = s * ap + c * aq;
+                const double vp = V[r * K + p], vq = V[r * K + q];
+                V[r * K + p] = c * vp - s * vq;
+                V[r * K + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+            for (int t = tid; t < (m / 2) * n; t += nt) {       // A <- J^T A
+                const int pi = t / n, cc = t - pi * n;
+                const int p = pr[pi][0], q = pr[pi][1];
+                if (q >= n) continue;
+                const double c = cs[pi][0], s = cs[pi][1];
+                const double ap = A[p * K + cc], aq = A[q * K + cc];
+                A[p * K + cc] = c * ap - s * aq;
+                A[q * K + cc] = s * ap + c * aq;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------- dense steps
+// val: the reduced values of the preceding basis product (see OP_* codes).
+__device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_solve_info *info)
+{
+    __shared__ double Ms[K * K], Ls[K * K], Vs[K * K];
+    __shared__ double ys[K + 1], gs[K + 1], sg[K + 1];
+    __shared__ double cs2[2];
+    __shared__ int ord[K];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int k = sq->k;
+    switch (op) {
+    case OP_SPE_START: {
+        // g = q^T b, H y = g, x0 = q y, r0 = b - K q y
+        for (int i = tid; i < k; i += nt) gs[i] = sq->s[i] * val[i];
+        __syncthreads();
+        bool good = k > 0;
+        if (good) good = chol_solve(sq->H, Ls, ys, gs, k);
+        if (tid == 0) {
+            sq->flags = (k > 0 && !good) ? 1 : 0;
+            sq->zero_start = good ? 0 : 1;
+            sq->a1 = 0.0;
+            sq->a2 = 1.0;
+            sq->ncol_md = good ? k : 0;
+            for (int i = 0; i < K; ++i) {
+                const double c = (good && i < k) ? ys[i] * sq->s[i] : 0.0;
+                sq->cA[i] = c;
+                sq->cB[i] = -c;
+            }
+            sq->active = 1;
+        }
+        break;
+    }
+    case OP_SPE_PUSH1: {
+        // c1 = q^T x; w = x - q c1
+        if (tid == 0) {
+            const double xx = val[k];
+            sq->xnorm = sqrt(xx);
+            sq->active = (xx > 0.0 && xx <= 1e300) ? 1 : 0;
+            for (int i = 0; i < K; ++i) {
+                const double c1 = i < k ? sq->s[i] * val[i] : 0.0;
+                sq->c1[i] = c1;
+                sq->cA[i] = i < k ? -c1 * sq->s[i] : 0.0;
+            }
+            sq->a1 = 1.0;
+            sq->slot_new = k;
+            sq->ncol_md = k;
+            sq->accept = 0;     // set by OP_SPE_PUSH3 for an accepted column
+            sq->rotate = 0;     // set by OP_SPE_PUSH4 when the window slides
+        }
+        break;
+    }
+    case OP_SPE_PUSH2: {
+        // second pass: c2 = q^T w; x2 = w - q c2
+        if (tid == 0) {
+            for (int i = 0; i < K; ++i) {
+                const double c2 = i < k ? sq->s[i] * val[i] : 0.0;
+                sq->c2[i] = c2;
+                sq->cA[i] = i < k ? -c2 * sq->s[i] : 0.0;
+            }
+            sq->a1 = 1.0;
+        }
+        break;
+    }
+    case OP_SPE_PUSH3: {
+        // accept x2 if it is not (numerically) in span(q): a linearly
+        // independent new column
+        if (tid == 0) {
+            const double rho = sqrt(val[0]);
+            sq->rho = rho;
+            const int acc = (sq->active && rho > tol * sq->xnorm && k + 1 < K) ? 1 : 0;
+            sq->accept = acc;
+            sq->active = acc;
+            if (acc) sq->s[k] = 1.0 / rho;
+            sq->ncol_md = k + 1;
+        }
+        break;
+    }
+    case OP_SPE_PUSH4: {
+        // new row/column of H = q^T K q and of the window coordinates R
+        if (tid == 0) {
+            sq->rotate = 0;
+            if (sq->accept) {
+                const double sk = sq->s[k];
+                for (int i = 0; i <= k; ++i) {
+                    const double h = sq->s[i] * sk * val[i];
+                    sq->H[i * K + k] = h;
+                    sq->H[k * K + i] = h;
+                }
+                for (int i = 0; i < k; ++i) sq->R[i * K + k] = sq->c1[i] + sq->c2[i];
+                sq->R[k * K + k] = sq->rho;
+                for (int j = 0; j < k; ++j) sq->R[k * K + j] = 0.0;
+                sq->k = k + 1;
+                sq->w = sq->w + 1;
+            }
+        }
+        __syncthreads();
+        if (!(sq->accept && sq->w > sq->cap)) break;
+        // Drop the oldest solution: R' = R[:, 1:] (n x n-1) is upper
+        // Hessenberg; Givens rotations Gt make Gt R' upper triangular with a
+        // zero last row, so the window is spanned by the first n-1 columns of
+        // q Gt^T; H' = Gt H Gt^T.
+        const int n = sq->k;
+        for (int t = tid; t < K * K; t += nt) {
+            const int i = t / K, j = t - i * K;
+            Ls[t] = (i < n && j < n - 1) ? sq->R[i * K + j + 1] : 0.0;
+            Ms[t] = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < n - 1; ++j) {
+            if (tid == 0) {
+                const double a0 = Ls[j * K + j], b0 = Ls[(j + 1) * K + j];
+                const double r = hypot(a0, b0);
+                cs2[0] = r > 0.0 ? a0 / r : 1.0;
+                cs2[1] = r > 0.0 ? b0 / r : 0.0;
+            }
+            __syncthreads();
+            const double c = cs2[0], sn = cs2[1];
+            for (int col = tid; col < n; col += nt) {
+                if (col < n - 1) {
+                    const double u = Ls[j * K + col], v = Ls[(j + 1) * K + col];
+                    Ls[j * K + col] = c * u + sn * v;
+                    Ls[(j + 1) * K + col] = -sn * u + c * v;
+                }
+                const double u = Ms[j * K + col], v = Ms[(j + 1) * K + col];
+                Ms[j * K + col] = c * u + sn * v;
+                Ms[(j + 1) * K + col] = -sn * u + c * v;
+            }
+            __syncthreads();
+        }
+        for (int t = tid; t < n * n; t += nt) {               // Vs = Gt H
+            const int i = t / n, j = t - i * n;
+            double s = 0.0;
+            for (int l = 0; l < n; ++l) s += Ms[i * K + l] * sq->H[l * K + j];
+            Vs[i * K + j] = s;
+        }
+        __syncthreads();
+        for (int t = tid; t < K * K; t += nt) {
+            const int i = t / K, j = t - i * K;
+            double h = 0.0;
+            if (i < n - 1 && j < n - 1)
+                for (int l = 0; l < n; ++l) h += Vs[i * K + l] * Ms[j * K + l];
+            sq->H[t] = h;
+            sq->R[t] = (i < n - 1 && j < n - 1) ? Ls[t] : 0.0;
+            // raw-column coefficients of the new basis: rot[i][j] = Gt[j][i] s_i
+            sq->rot[t] = (i < n && j < n - 1) ? Ms[j * K + i] * sq->s[i] : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = 0; i <= K; ++i) sq->s[i] = 1.0;
+            sq->rot_in = n;
+            sq->rot_k = n - 1;
+            sq->k = n - 1;
+            sq->w = n - 1;
+            sq->rotate = 1;
+        }
+        break;
+    }
+    case OP_POD_PUSH: {
+        // new row/column of G = X^T X and H = X^T K X at the ring slot
+        if (tid == 0) {
+            const int s = sq->slot_new, nc = sq->npush;
+            for (int i = 0; i < nc; ++i) {
+                sq->G[i * K + s] = val[2 * i];
+                sq->G[s * K + i] = val[2 * i];
+                sq->H[i * K + s] = val[2 * i + 1];
+                sq->H[s * K + i] = val[2 * i + 1];
+            }
+            sq->count = nc;
+            sq->head = (sq->head + 1) % sq->cap;
+            sq->slot_new = sq->head;
+            sq->npush = sq->count < sq->cap ? sq->count + 1 : sq->cap;
+        }
+        break;
+    }
+    case OP_POD_START: {
+        const int n = sq->count;
+        if (n == 0) {
+            if (tid == 0) {
+                sq->zero_start = 1; sq->kpod = 0; sq->pod_info = 1.0; sq->flags = 0;
+                sq->a1 = 0.0; sq->a2 = 1.0; sq->ncol_md = 0; sq->active = 1;
+                for (int i = 0; i < K; ++i) { sq->cA[i] = 0.0; sq->cB[i] = 0.0; }
+            }
+            break;
+        }
+        // warm start from the previous eigenvectors: A0 = V^T G V
+        for (int t = tid; t < K * K; t += nt) Vs[t] = sq->V[t];
+        __syncthreads();
+        for (int t = tid; t < n * n; t += nt) {
+            const int i = t / n, j = t - i * n;
+            double s = 0.0;
+            for (int l = 0; l < n; ++l) s += sq->G[i * K + l] * Vs[l * K + j];
+            Ls[i * K + j] = s;
+        }
+        __syncthreads();
+        for (int t = tid; t < n * n; t += nt) {
+            const int i = t / n, j = t - i * n;
+            double s = 0.0;
+            for (int l = 0; l < n; ++l) s += Vs[l * K + i] * Ls[l * K + j];
+            Ms[i * K + j] = s;
+        }
+        __syncthreads();
+        jacobi_eig(Ms, Vs, n);
+        if (tid == 0) {
+            for (int i = 0; i < n; ++i) ord[i] = i;
+            for (int i = 0; i < n; ++i)
+                for (int j = i + 1; j < n; ++j)
+                    if (Ms[ord[j] * K + ord[j]] > Ms[ord[i] * K + ord[i]]) {
+                        const int t = ord[i]; ord[i] = ord[j]; ord[j] = t;
+                    }
+            double tot = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double l = Ms[ord[i] * K + ord[i]];
+                sg[i] = l > 0.0 ? sqrt(l) : 0.0;
+                tot += sg[i];
+            }
+            int kp = 0;
+            for (int i = 0; i < n; ++i)
+                if (sg[i] > 0.0 && sg[i] >= sq->pod_eps * sg[0]) ++kp;
+            if (kp > sq->pod_kmax) kp = sq->pod_kmax;
+            double kept = 0.0;
+            for (int i = 0; i < kp; ++i) kept += sg[i];
+            sq->kpod = kp;
+            sq->pod_info = tot > 0.0 ? kept / tot : 1.0;
+            for (int i = 0; i < n; ++i) sq->lam[i] = sg[i];
+        }
+        __syncthreads();
+        for (int t = tid; t < K * K; t += nt) {                // sorted eigenvectors
+            const int i = t / K, j = t - i * K;
+            sq->V[t] = (i < n && j < n) ? Vs[i * K + ord[j]] : (i == j ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        const int kp = sq->kpod;
+        for (int t = tid; t < n * kp; t += nt) {               // Ls = H V_k
+            const int l = t / kp, b2 = t - l * kp;
+            double h = 0.0;
+            for (int m2 = 0; m2 < n; ++m2) h += sq->H[l * K + m2] * sq->V[m2 * K + b2];
+            Ls[l * K + b2] = h;
+        }
+        __syncthreads();
+        for (int t = tid; t < kp * kp; t += nt) {              // Sigma^-1 V_k^T H V_k Sigma^-1
+            const int a2 = t / kp, b2 = t - a2 * kp;
+            double h = 0.0;
+            for (int l = 0; l < n; ++l) h += sq->V[l * K + a2] * Ls[l * K + b2];
+            Ms[a2 * K + b2] = h / (sg[a2] * sg[b2]);
+        }
+        for (int a2 = tid; a2 < kp; a2 += nt) {                // Sigma^-1 V_k^T X^T b
+            double s = 0.0;
+            for (int l = 0; l < n; ++l) s += sq->V[l * K + a2] * val[l];
+            gs[a2] = s / sg[a2];
+        }
+        __syncthreads();
+        bool good = kp > 0;
+        if (good) good = chol_solve(Ms, Ls, ys, gs, kp);
+        if (tid == 0) {
+            // z = V_k Sigma_k^-1 y ; x0 = X z ; r0 = b - (K X) z
+            for (int l = 0; l < K; ++l) {
+                double z = 0.0;
+                if (good && l < n)
+                    for (int j = 0; j < kp; ++j) z += sq->V[l * K + j] * ys[j] / sg[j];
+                sq->cA[l] = z;
+                sq->cB[l] = -z;
+            }
+            sq->flags = (kp > 0 && !good) ? 1 : 0;
+            sq->zero_start = good ? 0 : 1;
+            sq->a1 = 0.0;
+            sq->a2 = 1.0;
+            sq->ncol_md = good ? n : 0;
+            sq->active = 1;
+        }
+        break;
+    }
+    default:
+        break;
+    }
+    if (info && tid == 0 && (op == OP_SPE_START || op == OP_POD_START)) {
+        info->basis_cols = op == OP_POD_START ? sq->kpod : sq->k;
+        info->pod_info = op == OP_POD_START ? sq->pod_info : 1.0;
+    }
+    __syncthreads();
+}
+
+// Deterministic reduction of nvals values over kMdBlocks partial rows into
+// the shared val[] (all threads of the last block).
+__device__ void reduce_rows(const double *part, int nvals, double *val)
+{
+    __shared__ double tmp[16][17];
+    const int tid = threadIdx.x;
+    const int vq = tid & 15, gq = tid >> 4;     // 16 values x 16 block groups
+    for (int c0 = 0; c0 < nvals; c0 += 16) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (c0 + vq < nvals) {
+            for (int b = gq; b < kMdBlocks; b += 64) {
+                const double *P = part + c0 + vq;
+                s0 += P[(int64_t)b * kMdStride];
+                if (b + 16 < kMdBlocks) s1 += P[(int64_t)(b + 16) * kMdStride];
+                if (b + 32 < kMdBlocks) s2 += P[(int64_t)(b + 32) * kMdStride];
+                if (b + 48 < kMdBlocks) s3 += P[(int64_t)(b + 48) * kMdStride];
+            }
+        }
+        tmp[gq][vq] = (s0 + s1) + (s2 + s3);
+        __syncthreads();
+        if (tid < 16 && c0 + tid < nvals) {
+            double t = 0.0;
+            for (int g2 = 0; g2 < 16; ++g2) t += tmp[g2][tid];
+            val[c0 + tid] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------- basis products
+// part[block][i*nb + j] = sum over rows of A_i B_j for p = k (+1 with
+// a_extra) columns of A and nb <= 4 vectors B.  One wave handles 16 rows per
+// step: lane (m = lane % 16, kq = lane / 16) loads 4 consecutive rows of A
+// column m (and of B_m), so each 16-lane group reads full 128-byte lines;
+// the four rows feed four v_mfma_f64_16x16x4f64 (K index kq = group), i.e.
+// C[m][j] += A_m[row] B_j[row].
+__device__ __forceinline__ void load4(const double *col, int64_t row, int64_t n, double (&v)[4])
+{
+    if (!col) {
+        v[0] = v[1] = v[2] = v[3] = 0.0;
+        return;
+    }
+    if (row + 3 < n) {
+        const double2 *p = reinterpret_cast<const double2 *>(col + row);
+        const double2 u0 = p[0], u1 = p[1];
+        v[0] = u0.x; v[1] = u0.y; v[2] = u1.x; v[3] = u1.y;
+    } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = (row + s < n) ? col[row + s] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_multidot(MdArgs a)
+{
+    if (a.active && !*a.active) return;
+    __shared__ double red[4][32][4];
+    const int k = a.kp ? *a.kp : a.kfix;
+    const int p = k + (a.a_extra ? 1 : 0);
+    const int nb = a.nb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    auto colA = [&](int c) -> const double * {
+        if (c >= p) return nullptr;
+        return c < k ? a.A + (int64_t)c * a.ld : a.a_extra;
+    };
+    const double *cA0 = colA(m), *cA1 = colA(16 + m);
+    const double *cB = nullptr;
+    double bs = 1.0;
+    switch (m) {
+    case 0: if (nb > 0) { cB = a.B[0].p; bs = a.B[0].scale ? *a.B[0].scale : 1.0; } break;
+    case 1: if (nb > 1) { cB = a.B[1].p; bs = a.B[1].scale ? *a.B[1].scale : 1.0; } break;
+    case 2: if (nb > 2) { cB = a.B[2].p; bs = a.B[2].scale ? *a.B[2].scale : 1.0; } break;
+    case 3: if (nb > 3) { cB = a.B[3].p; bs = a.B[3].scale ? *a.B[3].scale : 1.0; } break;
+    default: break;
+    }
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int64_t n = a.n;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wv, nw = (int64_t)gridDim.x * 4;
+    for (int64_t r0 = gw * 16; r0 < n; r0 += nw * 16) {
+        const int64_t row = r0 + kq * 4;
+        double av0[4], av1[4], bv[4];
+        load4(cA0, row, n, av0);
+        load4(cB, row, n, bv);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bv[s] *= bs;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av0[s], bv[s], acc0, 0, 0, 0);
+        if (p > 16) {
+            load4(cA1, row, n, av1);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1[s], bv[s], acc1, 0, 0, 0);
+        }
+    }
+    // D layout (gfx950): lane l, element s holds C[4*s + l/16][l % 16]
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int row = 4 * s + kq;
+        if (m < 4) {
+            red[wv][row][m] = acc0[s];
+            red[wv][16 + row][m] = acc1[s];
+        }
+    }
+    __syncthreads();
+    const int nvals = p * nb;
+    if (threadIdx.x == 0) {
+        for (int t = 0; t < nvals; ++t) {
+            const int i = t / nb, j = t - i * nb;
+            const double s = ((red[0][i][j] + red[1][i][j]) + red[2][i][j]) + red[3][i][j];
+            a.part[(int64_t)blockIdx.x * kMdStride + t] = s;
+        }
+    }
+}
+
+void multidot(const MdArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks), dim3(256), 0, st, a);
+}
+
+// ----------------------------------------------------- linear combinations
+// y1 = a1 v1 + sum_{i<k} cA_i A_i        (y1 may be column *slot of A)
+// y2 = a2 s2 v2 + sum_{i<k} cB_i B_i
+// partials: [0..k) A_i^T y1 (want_dots), then |y1|^2, |y2|^2, |s2 v2|^2
+__global__ void __launch_bounds__(256) k_lincomb(LcArgs a)
+{
+    if (a.active && !*a.active) return;
+    __shared__ double sA[kMaxWin], sB[kMaxWin];
+    __shared__ double lds[kMaxWin + 3][4];
+    const int k = a.kp ? *a.kp : 0;
+    if (threadIdx.x < kMaxWin) {
+        sA[threadIdx.x] = (a.cA && (int)threadIdx.x < k) ? a.cA[threadIdx.x] : 0.0;
+        sB[threadIdx.x] = (a.cB && (int)threadIdx.x < k) ? a.cB[threadIdx.x] : 0.0;
+    }
+    __syncthreads();
+    double *y1 = a.y1;
+    if (a.slot) y1 = const_cast<double *>(a.A) + (int64_t)(*a.slot) * a.ld;
+    const double a1 = a.a1 ? *a.a1 : 0.0, a2 = a.a2 ? *a.a2 : 0.0;
+    const double s2 = a.v2.scale ? *a.v2.scale : 1.0;
+    double dots[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) dots[i] = 0.0;
+    double n1 = 0.0, n2 = 0.0, nbb = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < a.n; row += stride) {
+        double v = (a.v1 && a1 != 0.0) ? a1 * a.v1[row] : 0.0;
+        double u = 0.0;
+        for (int i = 0; i < k; ++i) {
+            v += sA[i] * a.A[(int64_t)i * a.ld + row];
+            if (a.y2) u += sB[i] * a.B[(int64_t)i * a.ld + row];
+        }
+        if (y1) {
+            y1[row] = v;
+            n1 += v * v;
+        }
+        if (a.y2) {
+            const double bv = a.v2.p ? s2 * a.v2.p[row] : 0.0;
+            u += a2 * bv;
+            a.y2[row] = u;
+            n2 += u * u;
+            nbb += bv * bv;
+        }
+        if (a.want_dots) {
+            // second sweep over the same rows (cache hits): A_i^T y1
+#pragma unroll
+            for (int i = 0; i < KC; ++i)
+                if (i < k) dots[i] += a.A[(int64_t)i * a.ld + row] * v;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nv = a.want_dots ? k : 0;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+        if (i < nv) {
+            const double s = wave_sum(dots[i]);
+            if (lane == 0) lds[i][wv] = s;
+        }
+    }
+    {
+        const double s0 = wave_sum(n1), s1 = wave_sum(n2), s2w = wave_sum(nbb);
+        if (lane == 0) {
+            lds[kMaxWin][wv] = s0;
+            lds[kMaxWin + 1][wv] = s1;
+            lds[kMaxWin + 2][wv] = s2w;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *P = a.part + (int64_t)blockIdx.x * kMdStride;
+        for (int i = 0; i < nv; ++i) P[i] = ((lds[i][0] + lds[i][1]) + lds[i][2]) + lds[i][3];
+        for (int q = 0; q < 3; ++q)
+            P[nv + q] = ((lds[kMaxWin + q][0] + lds[kMaxWin + q][1]) + lds[kMaxWin + q][2]) +
+                        lds[kMaxWin + q][3];
+    }
+}
+
+void lincomb(const LcArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks), dim3(256), 0, st, a);
+}
+
+// In-place rotation of the first rot_in columns of A (and B) into rot_k
+// columns: A'_j = sum_i rot[i][j] A_i.
+__global__ void __launch_bounds__(256)
+    k_rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq)
+{
+    if (!seq->rotate) return;
+    __shared__ double R[K * K];
+    const int kin = seq->rot_in, kout = seq->rot_k;
+    for (int t = threadIdx.x; t < K * K; t += blockDim.x) R[t] = seq->rot[t];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n; row += stride) {
+#pragma unroll 1
+        for (int pass = 0; pass < 2; ++pass) {
+            double *M = pass == 0 ? A : B;
+            double v[KC];
+#pragma unroll
+            for (int i = 0; i < KC; ++i) v[i] = i < kin ? M[(int64_t)i * ld + row] : 0.0;
+#pragma unroll 1
+            for (int j = 0; j < kout; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < KC; ++i) s += R[i * K + j] * v[i];
+                M[(int64_t)j * ld + row] = s;
+            }
+        }
+    }
+}
+
+void rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rotate, dim3(kMdBlocks), dim3(256), 0, st, A, B, ld, n, seq);
+}
+
+// One block: reduce the partial rows of the preceding basis product, then
+// run the dense step `op` of the sequence.
+__global__ void __launch_bounds__(256)
+    k_small(SeqDev *sq, int op, const double *part, int nvals, double tol, ec_solve_info *info)
+{
+    __shared__ double val[kMdStride];
+    if (part) reduce_rows(part, nvals, val);
+    __syncthreads();
+    small_op(sq, op, val, tol, info);
+}
+
+void small(SeqDev *seq, int op, const double *part, int nvals, double tol, ec_solve_info *info,
+           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_small, dim3(1), dim3(256), 0, st, seq, op, part, nvals, tol, info);
+}
+
+// -------------------------------------------------------- sequence state
+__global__ void k_seq_reset(SeqDev *sq)
+{
+    for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
+        sq->H[i] = 0.0; sq->R[i] = 0.0; sq->G[i] = 0.0; sq->rot[i] = 0.0;
+        sq->V[i] = (i % (K + 1)) == 0 ? 1.0 : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        sq->k = 0; sq->w = 0; sq->kpod = 0; sq->head = 0; sq->count = 0;
+        sq->accept = 0; sq->rotate = 0; sq->active = 0; sq->flags = 0; sq->zero_start = 1;
+        sq->ncol_md = 0; sq->npush = 1; sq->slot_new = 0; sq->pod_info = 1.0; sq->rot_in = 0;
+        sq->rot_k = 0;
+        for (int i = 0; i <= K; ++i) sq->s[i] = 1.0;
+    }
+}
+
+void seq_reset(SeqDev *seq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seq_reset, dim3(1), dim3(256), 0, st, seq);
+}
+
+__global__ void k_seq_config(SeqDev *sq, int method, int cap, int kmax, double eps)
+{
+    sq->method = method;
+    sq->cap = cap;
+    sq->pod_kmax = kmax;
+    sq->pod_eps = eps;
+}
+
+void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seq_config, dim3(1), dim3(1), 0, st, seq, method, cap, kmax, eps);
+}
+
+}  // namespace ec

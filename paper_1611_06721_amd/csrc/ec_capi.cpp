@@ -1,0 +1,1040 @@
+// ec_capi.cpp -- host side of the C-ABI declared in ec.h: problem assembly
+// and validation, workspace layout, and the launch sequences of solves,
+// start vectors and explicit Euler steps.  All arithmetic on edge arrays runs
+// in the kernels of ec_kernels.hip; this file only builds tables and drives.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ec.h"
+#include "ec_internal.h"
+
+using namespace ec;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr double kDepTol = 1e-10;   // SPE: drop a solution whose new direction is below this
+constexpr int64_t kAlign = 256;
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct ec_problem {
+    std::string err;
+    Geo g{};
+    Mats mats{};
+    int64_t npad = 0, S = 0, ncell = 0;
+    int nc = 0;
+    int64_t nn = 0;
+    std::vector<uint8_t> cls, cmat;
+    std::vector<int> cslot;
+    std::vector<double> minv, msig;
+    std::vector<double> xs;
+    int has_cond = 0;
+    int bblo[3] = {0, 0, 0}, bbhi[3] = {-1, -1, -1};
+    int band_lo[3] = {0, 0, 0}, band_hi[3] = {-1, -1, -1};
+    int wf = 0;
+    double amp = 0, freq = 0, tau = 1;
+    int64_t ramp = 1;
+    // bound state
+    bool bound = false;
+    hipStream_t st = nullptr;
+    char *ws = nullptr;
+    int64_t ws_bytes = 0;
+    int cap = 0;
+    int64_t ld = 0;
+    // FP64 edge vectors: state, source, CG buffers, scratch
+    double *xs_d = nullptr, *sj = nullptr, *sc = nullptr, *ac = nullptr, *bcpl = nullptr;
+    double *rb[2] = {}, *wb[2] = {}, *sb[2] = {}, *pv = nullptr;
+    double *w = nullptr, *t2 = nullptr, *t3 = nullptr, *t4 = nullptr;
+    // FP32 vectors of the refinement's inner solve
+    float *frb[2] = {}, *fwb[2] = {}, *fsb[2] = {}, *fpv = nullptr, *fd = nullptr;
+    double *hist[EC_NSEQ] = {};
+    uint8_t *cls_d = nullptr, *cmat_d = nullptr;
+    int *cslot_d = nullptr;
+    double *minv_d = nullptr, *cvec_d = nullptr;
+    Mats *mats_d = nullptr;
+    SeqDev *seq_d = nullptr;
+    Ctrl *ctrl_d = nullptr;
+    CgCtl *cg_d = nullptr;
+    double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr;
+    int seq_method[EC_NSEQ], seq_win[EC_NSEQ], seq_kmax[EC_NSEQ];
+    double seq_eps[EC_NSEQ];
+    int hint[EC_NSEQ];
+    int cg_blocks = 0, tiles = 0;
+    // host polling of the CG done flag (eager mode)
+    int *pin = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~ec_problem()
+    {
+        if (pin) (void)hipHostFree(pin);
+        for (hipEvent_t &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// ---------------------------------------------------------------- errors
+static int32_t fail(ec_problem *h, int32_t code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIP_TRY(h, expr)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(h, EC_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+static int32_t launch_check(ec_problem *h, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(h, EC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return EC_OK;
+}
+
+static bool aligned(const void *p) { return p && ((uintptr_t)p % 16 == 0); }
+
+// ------------------------------------------------------------- assembly
+// Edge (c, i, j, k) of the padded layout
+static inline int64_t slot(const ec_problem *h, int c, int i, int j, int k)
+{
+    return (int64_t)c * h->S + ((int64_t)k * (h->g.ny + 1) + j) * (h->g.nx + 1) + i;
+}
+
+static int32_t assemble(ec_problem *h, const ec_grid *grid, const ec_materials *mat,
+                        const ec_source *src)
+{
+    const int nx = grid->n[0], ny = grid->n[1], nz = grid->n[2];
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 1023 || ny > 1023 || nz > 1023)
+        return fail(nullptr, EC_ERR_ARG, "grid: each axis needs 2..1023 cells");
+    if (!(grid->len[0] > 0 && grid->len[1] > 0 && grid->len[2] > 0))
+        return fail(nullptr, EC_ERR_ARG, "grid: lengths must be positive");
+    const int64_t nodes = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    if (nodes >= (int64_t)1 << 25)
+        return fail(nullptr, EC_ERR_ARG, "grid: at most 2^25 nodes");
+    if (!mat || !mat->cell_mat || mat->n_mats < 0 || mat->n_mats >= kMaxMat ||
+        (mat->n_mats > 0 && !mat->mats) || !(mat->nu0 > 0))
+        return fail(nullptr, EC_ERR_ARG, "materials: bad descriptor (n_mats < %d, nu0 > 0)",
+                    kMaxMat);
+    Geo &g = h->g;
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.px = nx + 1; g.py = ny + 1;
+    g.S = nodes;
+    g.npad = 3 * nodes;
+    g.hx = grid->len[0] / nx; g.hy = grid->len[1] / ny; g.hz = grid->len[2] / nz;
+    h->S = nodes;
+    h->npad = 3 * nodes;
+    h->ncell = (int64_t)nx * ny * nz;
+    Mats &M = h->mats;
+    M.n = mat->n_mats + 1;
+    M.nu0 = mat->nu0;
+    M.sig[0] = 0.0; M.k1[0] = 0.0; M.k2[0] = 0.0; M.k3[0] = mat->nu0;
+    for (int m = 0; m < mat->n_mats; ++m) {
+        const ec_material &e = mat->mats[m];
+        if (!(e.sigma > 0) || !std::isfinite(e.sigma) || !(e.k1 >= 0) || !std::isfinite(e.k2) ||
+            !(e.k3 > 0) || !std::isfinite(e.k1) || !std::isfinite(e.k3))
+            return fail(nullptr, EC_ERR_ARG,
+                        "material %d: need sigma > 0, k1 >= 0, k3 > 0 and finite k2", m + 1);
+        M.sig[m + 1] = e.sigma; M.k1[m + 1] = e.k1; M.k2[m + 1] = e.k2; M.k3[m + 1] = e.k3;
+    }
+    // Face weights of the nonconducting region: nu0 * dual edge / face area
+    g.wx = mat->nu0 * g.hx / (g.hy * g.hz);
+    g.wy = mat->nu0 * g.hy / (g.hz * g.hx);
+    g.wz = mat->nu0 * g.hz / (g.hx * g.hy);
+    // Jacobi: an edge off the conductor has four nonconducting faces
+    g.dinv[0] = 1.0 / (2.0 * (g.wy + g.wz));
+    g.dinv[1] = 1.0 / (2.0 * (g.wz + g.wx));
+    g.dinv[2] = 1.0 / (2.0 * (g.wx + g.wy));
+
+    h->cmat.assign(mat->cell_mat, mat->cell_mat + h->ncell);
+    int lo[3] = {nx, ny, nz}, hi[3] = {-1, -1, -1};
+    int64_t ncond = 0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int m = h->cmat[((int64_t)k * ny + j) * nx + i];
+                if (m > mat->n_mats)
+                    return fail(nullptr, EC_ERR_ARG, "cell_mat: id %d beyond n_mats", m);
+                if (m) {
+                    ++ncond;
+                    lo[0] = std::min(lo[0], i); hi[0] = std::max(hi[0], i);
+                    lo[1] = std::min(lo[1], j); hi[1] = std::max(hi[1], j);
+                    lo[2] = std::min(lo[2], k); hi[2] = std::max(hi[2], k);
+                }
+            }
+    h->has_cond = ncond > 0;
+    for (int a = 0; a < 3; ++a) { h->bblo[a] = lo[a]; h->bbhi[a] = hi[a]; }
+    const int64_t bvol = ncond ? (int64_t)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1) : 0;
+    g.box = (bvol == ncond) ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        g.clo[a] = ncond ? lo[a] : 1;
+        g.chi[a] = ncond ? hi[a] : 0;
+    }
+    // Edge classes and M_sigma: sigma of the (up to four) cells around an
+    // edge, a quarter of the dual face each, over the edge length.
+    h->cls.assign(h->npad, 0);
+    h->msig.assign(h->npad, 0.0);
+    const int n3[3] = {nx, ny, nz};
+    const double hh[3] = {g.hx, g.hy, g.hz};
+    for (int c = 0; c < 3; ++c) {
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        const double quarter = hh[a1] * hh[a2] / 4.0 / hh[c];
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i <= nx; ++i) {
+                    const int idx[3] = {i, j, k};
+                    if (idx[c] >= n3[c]) continue;                           // padding
+                    if (idx[a1] == 0 || idx[a1] == n3[a1] || idx[a2] == 0 || idx[a2] == n3[a2])
+                        continue;                                            // Dirichlet
+                    double s = 0.0;
+                    for (int d1 = -1; d1 <= 0; ++d1)
+                        for (int d2 = -1; d2 <= 0; ++d2) {
+                            int cc[3] = {i, j, k};
+                            cc[a1] += d1;
+                            cc[a2] += d2;
+                            s += M.sig[h->cmat[((int64_t)cc[2] * ny + cc[1]) * nx + cc[0]]];
+                        }
+                    const int64_t e = slot(h, c, i, j, k);
+                    h->msig[e] = s * quarter;
+                    h->cls[e] = s > 0.0 ? 1 : 2;
+                }
+    }
+    h->cslot.clear();
+    h->minv.clear();
+    h->nn = 0;
+    for (int64_t e = 0; e < h->npad; ++e) {
+        if (h->cls[e] == 1) {
+            h->cslot.push_back((int)e);
+            h->minv.push_back(1.0 / h->msig[e]);
+        } else if (h->cls[e] == 2) {
+            ++h->nn;
+        }
+    }
+    h->nc = (int)h->cslot.size();
+    // band of nonconducting edges coupled to the conductor (K_cn^T support)
+    for (int a = 0; a < 3; ++a) {
+        h->band_lo[a] = std::max(0, lo[a] - 1);
+        h->band_hi[a] = std::min(n3[a], hi[a] + 2);
+    }
+    // Source
+    if (!src || !src->edge_current)
+        return fail(nullptr, EC_ERR_ARG, "source: edge_current is required");
+    if (src->waveform < EC_WF_DC || src->waveform > EC_WF_EXP)
+        return fail(nullptr, EC_ERR_ARG, "source: unknown waveform %d", src->waveform);
+    if (src->waveform == EC_WF_RAMP && src->ramp_steps < 1)
+        return fail(nullptr, EC_ERR_ARG, "source: ramp_steps must be >= 1");
+    if (src->waveform == EC_WF_EXP && !(src->tau > 0))
+        return fail(nullptr, EC_ERR_ARG, "source: tau must be positive");
+    h->wf = src->waveform; h->amp = src->amp; h->freq = src->freq; h->tau = src->tau;
+    h->ramp = src->ramp_steps;
+    h->xs.assign(src->edge_current, src->edge_current + h->npad);
+    double jmax = 0.0;
+    for (int64_t e = 0; e < h->npad; ++e) {
+        const double v = h->xs[e];
+        if (!std::isfinite(v)) return fail(nullptr, EC_ERR_ARG, "source: non-finite entry");
+        if (v != 0.0 && h->cls[e] != 2)
+            return fail(nullptr, EC_ERR_ARG,
+                        "source: X_S must vanish off the nonconducting edges (slot %lld)",
+                        (long long)e);
+        jmax = std::max(jmax, std::fabs(v));
+    }
+    // discrete divergence G^T X_S at every node
+    double dmax = 0.0;
+    for (int k = 0; k <= nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i <= nx; ++i) {
+                double d = 0.0;
+                if (i < nx) d -= h->xs[slot(h, 0, i, j, k)];
+                if (i > 0) d += h->xs[slot(h, 0, i - 1, j, k)];
+                if (j < ny) d -= h->xs[slot(h, 1, i, j, k)];
+                if (j > 0) d += h->xs[slot(h, 1, i, j - 1, k)];
+                if (k < nz) d -= h->xs[slot(h, 2, i, j, k)];
+                if (k > 0) d += h->xs[slot(h, 2, i, j, k - 1)];
+                dmax = std::max(dmax, std::fabs(d));
+            }
+    if (dmax > 1e-10 * jmax)
+        return fail(nullptr, EC_ERR_ARG,
+                    "source: X_S is not divergence free (|G^T X_S| = %g, |X_S| = %g)", dmax, jmax);
+    return EC_OK;
+}
+
+extern "C" int32_t ec_create(const ec_grid *grid, const ec_materials *mat, const ec_source *src,
+                             ec_handle *out)
+{
+    if (!out) return fail(nullptr, EC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid) return fail(nullptr, EC_ERR_ARG, "grid is NULL");
+    ec_problem *h = new (std::nothrow) ec_problem();
+    if (!h) return fail(nullptr, EC_ERR_ARG, "out of host memory");
+    int32_t st;
+    try {
+        st = assemble(h, grid, mat, src);
+    } catch (...) {
+        st = fail(nullptr, EC_ERR_ARG, "host allocation failed");
+    }
+    if (st != EC_OK) {
+        delete h;
+        return st;
+    }
+    for (int s = 0; s < EC_NSEQ; ++s) {
+        h->seq_method[s] = -1; h->seq_win[s] = 0; h->seq_kmax[s] = 0; h->seq_eps[s] = 0.0;
+    }
+    *out = h;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_destroy(ec_handle h)
+{
+    delete h;
+    return EC_OK;
+}
+
+// -------------------------------------------------------- workspace
+// Layout (256-byte aligned pieces):
+//   13 FP64 edge vectors, 5 FP32 edge vectors, per sequence 2 (cap+1) basis
+//   columns, tables (classes, cell materials, conducting slots, 1/M_sigma),
+//   sequence states, barrier, control block, reduction partials.
+static int64_t layout(ec_problem *h, int cap, char *base)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        const int64_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return base ? base + o : nullptr;
+    };
+    const int64_t ld = align_up(h->npad, 64);
+    double **vecs[] = {&h->xs_d, &h->sj, &h->sc, &h->ac, &h->bcpl, &h->rb[0], &h->rb[1],
+                       &h->wb[0], &h->wb[1], &h->sb[0], &h->sb[1], &h->pv, &h->w, &h->t2,
+                       &h->t3, &h->t4};
+    for (double **v : vecs) *v = (double *)take(ld * 8);
+    float **fv[] = {&h->frb[0], &h->frb[1], &h->fwb[0], &h->fwb[1], &h->fsb[0], &h->fsb[1],
+                    &h->fpv, &h->fd};
+    for (float **v : fv) *v = (float *)take(ld * 4);
+    for (int s = 0; s < EC_NSEQ; ++s) h->hist[s] = (double *)take(2 * (int64_t)(cap + 1) * ld * 8);
+    h->cls_d = (uint8_t *)take(h->npad);
+    h->cmat_d = (uint8_t *)take(h->ncell);
+    h->cslot_d = (int *)take((int64_t)std::max(h->nc, 1) * 4);
+    h->minv_d = (double *)take((int64_t)std::max(h->nc, 1) * 8);
+    h->cvec_d = (double *)take((int64_t)std::max(h->nc, 1) * 8);
+    h->mats_d = (Mats *)take(sizeof(Mats));
+    h->seq_d = (SeqDev *)take(sizeof(SeqDev) * EC_NSEQ);
+    h->ctrl_d = (Ctrl *)take(sizeof(Ctrl));
+    h->cg_d = (CgCtl *)take(2 * sizeof(CgCtl));
+    h->part_cg = (double *)take(2 * 4 * (int64_t)kMaxBlocks * 8);
+    h->part_md = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
+    h->part_ref = (double *)take(2 * (int64_t)kMaxBlocks * 8);
+    h->ld = ld;
+    return off;
+}
+
+extern "C" int32_t ec_sizes(ec_handle h, int32_t window_cap, int64_t *n_padded, int64_t *n_c,
+                            int64_t *n_n, int64_t *workspace_bytes)
+{
+    if (!h) return fail(nullptr, EC_ERR_ARG, "handle is NULL");
+    if (window_cap < 1 || window_cap > EC_MAX_WINDOW)
+        return fail(h, EC_ERR_ARG, "window_cap must be 1..%d", EC_MAX_WINDOW);
+    if (n_padded) *n_padded = h->npad;
+    if (n_c) *n_c = h->nc;
+    if (n_n) *n_n = h->nn;
+    if (workspace_bytes) {
+        ec_problem tmp;   // layout on a scratch copy: do not disturb bound pointers
+        tmp.npad = h->npad; tmp.S = h->S; tmp.ncell = h->ncell; tmp.nc = h->nc;
+        *workspace_bytes = layout(&tmp, window_cap, nullptr);
+    }
+    return EC_OK;
+}
+
+// Grid of the node kernels: one tile of 256 nodes per block up to kMaxBlocks
+// (then a block sweeps several tiles); a multiple of 8 for the XCD mapping.
+static int choose_blocks(ec_problem *h)
+{
+    const int64_t tiles = (h->S + kTile - 1) / kTile;
+    const int64_t b = std::min<int64_t>(align_up(tiles, 8), kMaxBlocks);
+    return (int)std::max<int64_t>(b, 8);
+}
+
+extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64_t bytes,
+                           int32_t window_cap)
+{
+    if (!h) return fail(nullptr, EC_ERR_ARG, "handle is NULL");
+    if (window_cap < 1 || window_cap > EC_MAX_WINDOW)
+        return fail(h, EC_ERR_ARG, "window_cap must be 1..%d", EC_MAX_WINDOW);
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
+        return fail(h, EC_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+    {
+        ec_problem tmp;
+        tmp.npad = h->npad; tmp.S = h->S; tmp.ncell = h->ncell; tmp.nc = h->nc;
+        const int64_t need = layout(&tmp, window_cap, nullptr);
+        if (bytes < need)
+            return fail(h, EC_ERR_ARG, "workspace too small: %lld < %lld bytes", (long long)bytes,
+                        (long long)need);
+    }
+    h->st = (hipStream_t)hip_stream;
+    h->ws = (char *)workspace;
+    h->ws_bytes = bytes;
+    h->cap = window_cap;
+    layout(h, window_cap, h->ws);
+    h->g.cls = h->cls_d;
+    hipStream_t st = h->st;
+    HIP_TRY(h, hipMemsetAsync(h->ws, 0, (size_t)bytes, st));
+    HIP_TRY(h, hipMemcpyAsync(h->xs_d, h->xs.data(), h->npad * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->cls_d, h->cls.data(), h->npad, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->cmat_d, h->cmat.data(), h->ncell, hipMemcpyHostToDevice, st));
+    if (h->nc) {
+        HIP_TRY(h, hipMemcpyAsync(h->cslot_d, h->cslot.data(), (size_t)h->nc * 4,
+                                  hipMemcpyHostToDevice, st));
+        HIP_TRY(h, hipMemcpyAsync(h->minv_d, h->minv.data(), (size_t)h->nc * 8,
+                                  hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(h, hipMemcpyAsync(h->mats_d, &h->mats, sizeof(Mats), hipMemcpyHostToDevice, st));
+    Ctrl c{};
+    c.one = 1.0;
+    c.worst = EC_OK;
+    HIP_TRY(h, hipMemcpyAsync(h->ctrl_d, &c, sizeof c, hipMemcpyHostToDevice, st));
+    for (int s = 0; s < EC_NSEQ; ++s) {
+        seq_config(h->seq_d + s, EC_SV_SPE, window_cap, window_cap, 1e-4, st);
+        seq_reset(h->seq_d + s, st);
+        h->seq_method[s] = -1;
+        h->hint[s] = 16;
+    }
+    HIP_TRY(h, hipStreamSynchronize(st));
+    if (!h->pin) HIP_TRY(h, hipHostMalloc((void **)&h->pin, 64, hipHostMallocDefault));
+    for (hipEvent_t &e : h->ev)
+        if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->tiles = (int)((h->S + kTile - 1) / kTile);
+    h->cg_blocks = choose_blocks(h);
+    h->bound = true;
+    return EC_OK;
+}
+
+#define NEED_BOUND(h)                                                                     \
+    do {                                                                                  \
+        if (!(h)) return fail(nullptr, EC_ERR_ARG, "handle is NULL");                     \
+        if (!(h)->bound) return fail((h), EC_ERR_STATE, "ec_bind first");                 \
+    } while (0)
+
+// --------------------------------------------------------- histories
+static double *basis_Q(ec_problem *h, int seq) { return h->hist[seq]; }
+static double *basis_KQ(ec_problem *h, int seq)
+{
+    return h->hist[seq] + (int64_t)(h->cap + 1) * h->ld;
+}
+
+static void seq_ensure(ec_problem *h, int seq, int method, int window, int kmax, double eps)
+{
+    if (method != EC_SV_SPE && method != EC_SV_POD) return;
+    if (h->seq_method[seq] == method && h->seq_win[seq] == window && h->seq_kmax[seq] == kmax &&
+        h->seq_eps[seq] == eps)
+        return;
+    seq_config(h->seq_d + seq, method, window, kmax, eps, h->st);
+    // the POD truncation parameters act on the next start vector only; a new
+    // method or window starts a new history
+    if (h->seq_method[seq] != method || h->seq_win[seq] != window) seq_reset(h->seq_d + seq, h->st);
+    h->seq_method[seq] = method;
+    h->seq_win[seq] = window;
+    h->seq_kmax[seq] = kmax;
+    h->seq_eps[seq] = eps;
+}
+
+static MdArgs md_args(ec_problem *h)
+{
+    MdArgs m{};
+    m.ld = h->ld;
+    m.part = h->part_md;
+    m.n = h->npad;
+    return m;
+}
+
+static LcArgs lc_args(ec_problem *h, int seq)
+{
+    LcArgs l{};
+    SeqDev *sd = h->seq_d + seq;
+    l.A = basis_Q(h, seq);
+    l.B = basis_KQ(h, seq);
+    l.ld = h->ld;
+    l.kp = &sd->ncol_md;
+    l.cA = sd->cA;
+    l.cB = sd->cB;
+    l.a1 = &sd->a1;
+    l.a2 = &sd->a2;
+    l.part = h->part_md;
+    l.n = h->npad;
+    return l;
+}
+
+static void dense(ec_problem *h, int seq, int op, ec_solve_info *info = nullptr)
+{
+    small(h->seq_d + seq, op, h->part_md, kMdStride, kDepTol, info, h->st);
+}
+
+// x0 and r0 = b - K_n x0 (into rb[0]) from the history of seq (eqs. 10, 14)
+static void seq_start(ec_problem *h, int seq, int method, const double *b, const double *bscale,
+                      double *x0, ec_solve_info *info)
+{
+    SeqDev *sd = h->seq_d + seq;
+    hipStream_t st = h->st;
+    MdArgs m = md_args(h);
+    m.A = basis_Q(h, seq);
+    m.kp = method == EC_SV_POD ? &sd->count : &sd->k;
+    m.B[0] = {b, bscale};
+    m.nb = 1;
+    multidot(m, st);
+    dense(h, seq, method == EC_SV_POD ? OP_POD_START : OP_SPE_START, info);
+    LcArgs l = lc_args(h, seq);
+    l.v2 = {b, bscale};
+    l.y1 = x0;
+    l.y2 = h->rb[0];
+    lincomb(l, st);
+}
+
+// append solution x to the history of seq
+static void seq_push(ec_problem *h, int seq, int method, const double *x)
+{
+    SeqDev *sd = h->seq_d + seq;
+    hipStream_t st = h->st;
+    double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
+    if (method == EC_SV_POD) {
+        // snapshot into the ring slot with its K_n product, then a Gram row
+        spmv_slot(h->g, x, h->t3, KQ, Q, &sd->slot_new, h->ld, nullptr, st);
+        MdArgs m = md_args(h);
+        m.A = Q;
+        m.kp = &sd->npush;
+        m.B[0] = {x, nullptr};
+        m.B[1] = {h->t3, nullptr};
+        m.nb = 2;
+        multidot(m, st);
+        dense(h, seq, OP_POD_PUSH);
+        return;
+    }
+    // SPE: two classical Gram-Schmidt passes against the orthogonal basis
+    MdArgs m = md_args(h);
+    m.A = Q;
+    m.kp = &sd->k;
+    m.a_extra = x;
+    m.B[0] = {x, nullptr};
+    m.nb = 1;
+    multidot(m, st);
+    dense(h, seq, OP_SPE_PUSH1);
+    LcArgs l = lc_args(h, seq);
+    l.v1 = x;
+    l.y1 = h->w;
+    l.active = &sd->active;
+    l.want_dots = 1;
+    lincomb(l, st);
+    dense(h, seq, OP_SPE_PUSH2);
+    l.v1 = h->w;
+    l.y1 = h->t2;
+    l.want_dots = 0;
+    lincomb(l, st);
+    dense(h, seq, OP_SPE_PUSH3);
+    spmv_slot(h->g, h->t2, h->t3, KQ, Q, &sd->slot_new, h->ld, &sd->active, st);
+    MdArgs m2 = md_args(h);
+    m2.A = KQ;
+    m2.kp = &sd->ncol_md;
+    m2.B[0] = {h->t2, nullptr};
+    m2.nb = 1;
+    m2.active = &sd->active;
+    multidot(m2, st);
+    dense(h, seq, OP_SPE_PUSH4);
+    rotate(Q, KQ, h->ld, h->npad, sd, st);
+}
+
+// ------------------------------------------------------------- solve
+static bool capturing(ec_problem *h)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(h->st, &cs);
+    return cs != hipStreamCaptureStatusNone;
+}
+
+constexpr int kGraphMaxIters = 4096;
+
+// Enqueue the iteration kernels of one CG solve.  Under graph capture a
+// fixed budget of maxit iterations is recorded (each returns at once after
+// convergence).  Eagerly, iterations go out in chunks and the host reads the
+// device done flag of the previous chunk (pinned copy) while the next chunk
+// runs; the first chunk is the previous iteration count of the sequence.
+template <typename T>
+static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hintable, int *n_issued)
+{
+    hipStream_t st = h->st;
+    const int maxit = a.maxit;
+    if (capturing(h)) {
+        const int budget = std::min(maxit, kGraphMaxIters);
+        for (int i = 0; i < budget; ++i) cg_iter<T>(a, i, st);
+        *n_issued = budget;
+        return launch_check(h, "cg (graph)");
+    }
+    int issued = 0, slot = 0, outstanding = -1;
+    int chunk = std::max(1, (hintable ? h->hint[seq] : 16) + 1);
+    bool first = true, done = false;
+    while (!done && issued < maxit) {
+        const int c = std::min(chunk, maxit - issued);
+        for (int j = 0; j < c; ++j) cg_iter<T>(a, issued + j, st);
+        issued += c;
+        HIP_TRY(h, hipMemcpyAsync(h->pin + 8 * slot, &a.ctl[issued & 1].it, 4 * sizeof(int),
+                                  hipMemcpyDeviceToHost, st));
+        HIP_TRY(h, hipEventRecord(h->ev[slot], st));
+        if (outstanding >= 0) {
+            HIP_TRY(h, hipEventSynchronize(h->ev[outstanding]));
+            done = h->pin[8 * outstanding + 1] != 0;
+        }
+        outstanding = slot;
+        slot ^= 1;
+        chunk = first ? std::max(2, chunk / 4) : std::min(2 * chunk, 256);
+        first = false;
+    }
+    if (outstanding >= 0) {
+        HIP_TRY(h, hipEventSynchronize(h->ev[outstanding]));
+        if (hintable) h->hint[seq] = std::max(0, h->pin[8 * outstanding]);
+    }
+    *n_issued = issued;
+    return launch_check(h, "cg");
+}
+
+static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const double *bscale,
+                        double *x, const ec_solve_opts *o, ec_solve_info *info)
+{
+    CgArgs<double> a{};
+    a.g = h->g;
+    a.x = x;
+    a.p = h->pv;
+    for (int i = 0; i < 2; ++i) { a.rb[i] = h->rb[i]; a.wb[i] = h->wb[i]; a.sb[i] = h->sb[i]; }
+    a.b = b;
+    a.bscale = bscale;
+    a.seq = h->seq_d + seq;
+    a.rtol = o->rtol;
+    a.maxit = o->maxit;
+    a.ctl = h->cg_d;
+    a.part = h->part_cg;
+    a.info = info;
+    a.ctrl = h->ctrl_d;
+    a.seq_id = seq;
+    a.accum = 0;
+    a.skip = nullptr;
+    a.tiles = h->tiles;
+    a.blocks = h->cg_blocks;
+    if (mode == START_X) {
+        a.mode = START_X;
+        cg_init<double>(a, h->st);
+        a.mode = START_R2;
+        cg_init<double>(a, h->st);
+    } else {
+        a.mode = mode;
+        cg_init<double>(a, h->st);
+    }
+    int issued = 0;
+    int32_t rc = cg_iterate<double>(h, a, seq, true, &issued);
+    if (rc) return rc;
+    cg_fin<double>(a, issued, h->st);
+    return launch_check(h, "cg fin");
+}
+
+// FP64 residual refinement around FP32 inner PCG solves of K_n d = r
+static int32_t run_refined(ec_problem *h, int seq, const double *b, const double *bscale,
+                           double *x, const ec_solve_opts *o, ec_solve_info *info)
+{
+    hipStream_t st = h->st;
+    const int outer = o->outer_max > 0 ? o->outer_max : 8;
+    refine_reset(h->ctrl_d, st);
+    for (int pass = 0; pass <= outer; ++pass) {
+        refine_residual(h->g, b, bscale, x, h->frb[0], h->part_ref, h->ctrl_d, h->cg_blocks, st);
+        refine_decide(h->part_ref, h->cg_blocks, h->ctrl_d, pass, outer, o->rtol, info,
+                      h->seq_d + seq, st);
+        if (pass == outer) break;
+        CgArgs<float> a{};
+        a.g = h->g;
+        a.x = h->fd;
+        a.p = h->fpv;
+        for (int i = 0; i < 2; ++i) { a.rb[i] = h->frb[i]; a.wb[i] = h->fwb[i]; a.sb[i] = h->fsb[i]; }
+        a.b = h->frb[0];      // the FP32 residual is the right-hand side (read in init only)
+        a.bscale = nullptr;
+        a.mode = START_ZERO;
+        a.seq = nullptr;
+        a.rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
+        a.maxit = o->inner_maxit > 0 ? o->inner_maxit : 200;
+        a.ctl = h->cg_d;
+        a.part = h->part_cg;
+        a.info = info;
+        a.ctrl = h->ctrl_d;
+        a.seq_id = seq;
+        a.accum = 1;
+        a.skip = &h->ctrl_d->refine_done;
+        a.tiles = h->tiles;
+        a.blocks = h->cg_blocks;
+        cg_init<float>(a, st);
+        int issued = 0;
+        int32_t rc = cg_iterate<float>(h, a, seq, false, &issued);
+        if (rc) return rc;
+        cg_fin<float>(a, issued, st);
+        refine_update(x, h->fd, h->ctrl_d, h->npad, st);
+    }
+    refine_final(x, h->ctrl_d, h->npad, st);
+    return launch_check(h, "refined solve");
+}
+
+static int32_t do_solve(ec_problem *h, int seq, int method, int window, int kmax, double eps,
+                        const double *b, const double *bscale, double *x, const ec_solve_opts *o,
+                        ec_solve_info *info, bool push)
+{
+    if (o->precision != EC_PREC_FP64 && o->precision != EC_PREC_FP32_REFINED)
+        return fail(h, EC_ERR_ARG, "unknown precision %d", o->precision);
+    if (!(o->rtol > 0) || o->maxit < 0) return fail(h, EC_ERR_ARG, "need rtol > 0, maxit >= 0");
+    int mode;
+    if (method == EC_SV_ZERO) {
+        mode = START_ZERO;
+    } else if (method == EC_SV_PREV) {
+        mode = START_X;
+    } else if (method == EC_SV_SPE || method == EC_SV_POD) {
+        if (window < 1 || window > h->cap)
+            return fail(h, EC_ERR_ARG, "window must be 1..%d (the bound window_cap)", h->cap);
+        seq_ensure(h, seq, method, window, kmax, eps);
+        seq_start(h, seq, method, b, bscale, x, info);
+        mode = START_DEV;
+    } else {
+        return fail(h, EC_ERR_ARG, "unknown start method %d", method);
+    }
+    int32_t rc;
+    if (o->precision == EC_PREC_FP64) {
+        rc = run_cg64(h, seq, mode, b, bscale, x, o, info);
+    } else {
+        if (mode == START_ZERO) fill(x, 0.0, h->npad, h->st);
+        rc = run_refined(h, seq, b, bscale, x, o, info);
+    }
+    if (rc != EC_OK) return rc;
+    if (push && (method == EC_SV_SPE || method == EC_SV_POD)) seq_push(h, seq, method, x);
+    return launch_check(h, "solve");
+}
+
+static bool valid_seq(int seq) { return seq >= 0 && seq < EC_NSEQ; }
+
+extern "C" int32_t ec_solve(ec_handle h, int32_t seq, int32_t method, int32_t window,
+                            const double *b, double *x, const ec_solve_opts *opts,
+                            ec_solve_info *dev_info)
+{
+    NEED_BOUND(h);
+    if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
+    if (!aligned(b) || !aligned(x) || !opts)
+        return fail(h, EC_ERR_ARG, "b, x must be 16-byte aligned device pointers; opts required");
+    const int kmax = (h->seq_method[seq] == method && h->seq_win[seq] == window) ? h->seq_kmax[seq]
+                                                                                  : window;
+    const double eps = (h->seq_method[seq] == method && h->seq_win[seq] == window)
+                           ? h->seq_eps[seq] : 1e-4;
+    return do_solve(h, seq, method, window, kmax, eps, b, nullptr, x, opts, dev_info, true);
+}
+
+extern "C" int32_t ec_history_reset(ec_handle h, int32_t seq)
+{
+    NEED_BOUND(h);
+    if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
+    seq_reset(h->seq_d + seq, h->st);
+    return launch_check(h, "history reset");
+}
+
+extern "C" int32_t ec_history_push(ec_handle h, int32_t seq, int32_t method, int32_t window,
+                                   const double *x)
+{
+    NEED_BOUND(h);
+    if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
+    if (method != EC_SV_SPE && method != EC_SV_POD)
+        return fail(h, EC_ERR_ARG, "history push needs SPE or POD");
+    if (window < 1 || window > h->cap) return fail(h, EC_ERR_ARG, "window must be 1..%d", h->cap);
+    if (!aligned(x)) return fail(h, EC_ERR_ARG, "x must be a 16-byte aligned device pointer");
+    const int kmax = (h->seq_method[seq] == method && h->seq_win[seq] == window) ? h->seq_kmax[seq]
+                                                                                  : window;
+    const double eps = (h->seq_method[seq] == method && h->seq_win[seq] == window)
+                           ? h->seq_eps[seq] : 1e-4;
+    seq_ensure(h, seq, method, window, kmax, eps);
+    seq_push(h, seq, method, x);
+    return launch_check(h, "history push");
+}
+
+extern "C" int32_t ec_start_vector(ec_handle h, int32_t seq, int32_t method, int32_t window,
+                                   int32_t pod_kmax, double pod_eps, const double *b, double *x0,
+                                   ec_solve_info *dev_info)
+{
+    NEED_BOUND(h);
+    if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
+    if (method != EC_SV_SPE && method != EC_SV_POD)
+        return fail(h, EC_ERR_ARG, "start vector needs SPE or POD");
+    if (window < 1 || window > h->cap) return fail(h, EC_ERR_ARG, "window must be 1..%d", h->cap);
+    if (pod_kmax < 1 || pod_kmax > window || !(pod_eps >= 0))
+        return fail(h, EC_ERR_ARG, "need 1 <= pod_kmax <= window and pod_eps >= 0");
+    if (!aligned(b) || !aligned(x0))
+        return fail(h, EC_ERR_ARG, "b, x0 must be 16-byte aligned device pointers");
+    seq_ensure(h, seq, method, window, pod_kmax, pod_eps);
+    seq_start(h, seq, method, b, nullptr, x0, dev_info);
+    return launch_check(h, "start vector");
+}
+
+// ------------------------------------------------------------- apply
+extern "C" int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y)
+{
+    NEED_BOUND(h);
+    if (!aligned(x) || !aligned(y) || x == y)
+        return fail(h, EC_ERR_ARG, "x, y must be distinct 16-byte aligned device pointers");
+    hipStream_t st = h->st;
+    int lo[3] = {0, 0, 0}, hi[3] = {h->g.nx, h->g.ny, h->g.nz};
+    switch (op) {
+    case EC_OP_KN:
+        mask_copy(h->g, x, h->t4, 2, st);
+        spmv(h->g, h->t4, y, lo, hi, st);
+        break;
+    case EC_OP_KCN_T:
+        mask_copy(h->g, x, h->t4, 1, st);
+        spmv(h->g, h->t4, y, lo, hi, st);
+        break;
+    case EC_OP_KC_KCN: {
+        fill(y, 0.0, h->npad, st);
+        UpdArgs u{};
+        u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
+        u.nc = h->nc; u.A = x; u.xn = x; u.nustate = x; u.out = y; u.apply = 1;
+        update_c(u, st);
+        break;
+    }
+    default:
+        return fail(h, EC_ERR_ARG, "unknown operator %d", op);
+    }
+    return launch_check(h, "apply");
+}
+
+// -------------------------------------------------------------- step
+static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const ec_step_opts *o,
+                         ec_solve_info *info)
+{
+    hipStream_t st = h->st;
+    step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st);
+    const int meth = o->start_method;
+    int32_t rc = do_solve(h, EC_SEQ_SRC, meth, o->window, o->pod_kmax, o->pod_eps, h->xs_d,
+                          &h->ctrl_d->scale, h->sj, &o->solve, info, true);
+    if (rc) return rc;
+    UpdArgs u{};
+    u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
+    u.nc = h->nc; u.A = A; u.sj = h->sj; u.sc = h->sc; u.out = h->ac; u.dt = dt; u.apply = 0;
+    u.ctrl = h->ctrl_d;
+    update_c(u, st);
+    if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
+    rc = do_solve(h, EC_SEQ_CPL, meth, o->window, o->pod_kmax, o->pod_eps, h->bcpl, nullptr, h->sc,
+                  &o->solve, info ? info + 1 : nullptr, true);
+    if (rc) return rc;
+    finish_state(h->g, A, h->ac, h->sj, h->sc, h->ctrl_d, 1, st);
+    return launch_check(h, "step");
+}
+
+static int32_t check_step_args(ec_problem *h, double dt, const double *A, const ec_step_opts *o)
+{
+    if (!aligned(A) || !o) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(h, EC_ERR_ARG, "dt must be positive");
+    const int m = o->start_method;
+    if (m < EC_SV_ZERO || m > EC_SV_POD) return fail(h, EC_ERR_ARG, "unknown start method");
+    if ((m == EC_SV_SPE || m == EC_SV_POD) &&
+        (o->window < 1 || o->window > h->cap || o->pod_kmax < 1 || o->pod_kmax > o->window ||
+         !(o->pod_eps >= 0)))
+        return fail(h, EC_ERR_ARG, "window 1..%d, 1 <= pod_kmax <= window, pod_eps >= 0", h->cap);
+    return EC_OK;
+}
+
+extern "C" int32_t ec_step(ec_handle h, int64_t m, double dt, double *A, const ec_step_opts *opts,
+                           ec_solve_info *dev_info)
+{
+    NEED_BOUND(h);
+    int32_t rc = check_step_args(h, dt, A, opts);
+    if (rc) return rc;
+    return step_impl(h, m, dt, A, opts, dev_info);
+}
+
+extern "C" int32_t ec_run(ec_handle h, int64_t m0, int64_t nsteps, double dt, double *A,
+                          const ec_step_opts *opts, ec_solve_info *dev_info)
+{
+    NEED_BOUND(h);
+    int32_t rc = check_step_args(h, dt, A, opts);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(h, EC_ERR_ARG, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        rc = step_impl(h, m0 + 1 + s, dt, A, opts, dev_info ? dev_info + 2 * s : nullptr);
+        if (rc) return rc;
+    }
+    return EC_OK;
+}
+
+extern "C" int32_t ec_set_state(ec_handle h, const double *A, const ec_solve_opts *opts)
+{
+    NEED_BOUND(h);
+    if (!aligned(A) || !opts) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
+    hipStream_t st = h->st;
+    fill(h->ac, 0.0, h->npad, st);
+    copy_c(h->cslot_d, h->nc, A, h->ac, st);
+    fill(h->bcpl, 0.0, h->npad, st);
+    if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
+    int32_t rc = do_solve(h, EC_SEQ_CPL, EC_SV_ZERO, 1, 1, 0.0, h->bcpl, nullptr, h->sc, opts,
+                          nullptr, false);
+    if (rc) return rc;
+    fill(h->sj, 0.0, h->npad, st);
+    for (int s = 0; s < EC_NSEQ; ++s) seq_reset(h->seq_d + s, st);
+    HIP_TRY(h, hipStreamSynchronize(st));
+    return launch_check(h, "set state");
+}
+
+extern "C" int32_t ec_set_step(ec_handle h, int64_t m)
+{
+    NEED_BOUND(h);
+    if (m < 0) return fail(h, EC_ERR_ARG, "m must be >= 0");
+    Ctrl c{};
+    HIP_TRY(h, hipMemcpyAsync(&c, h->ctrl_d, sizeof c, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    c.step = m;
+    HIP_TRY(h, hipMemcpyAsync(h->ctrl_d, &c, sizeof c, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    return EC_OK;
+}
+
+// ---------------------------------------------------------- counters
+extern "C" int32_t ec_counters(ec_handle h, int64_t *n_steps, int64_t *iters_src,
+                               int64_t *iters_cpl, int64_t *iters_adj, int32_t *worst_status)
+{
+    NEED_BOUND(h);
+    Ctrl c{};
+    HIP_TRY(h, hipMemcpyAsync(&c, h->ctrl_d, sizeof c, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    if (n_steps) *n_steps = c.n_steps;
+    if (iters_src) *iters_src = c.iters[EC_SEQ_SRC];
+    if (iters_cpl) *iters_cpl = c.iters[EC_SEQ_CPL];
+    if (iters_adj) *iters_adj = c.iters[EC_SEQ_ADJ];
+    if (worst_status) *worst_status = c.worst;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_counters_reset(ec_handle h)
+{
+    NEED_BOUND(h);
+    Ctrl c{};
+    HIP_TRY(h, hipMemcpyAsync(&c, h->ctrl_d, sizeof c, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    c.n_steps = 0;
+    for (int s = 0; s < EC_NSEQ; ++s) c.iters[s] = 0;
+    c.worst = EC_OK;
+    HIP_TRY(h, hipMemcpyAsync(h->ctrl_d, &c, sizeof c, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    return EC_OK;
+}
+
+// -------------------------------------------------------------- CFL
+// Power method on M_c^{-1} K_S (eq. 8) in the M_c inner product:
+//   s = K_n^+ K_cn^T v ;  g = [K_nu(A) (v (+) -s)]_C = K_S v ;
+//   lambda = v^T g (v M_c-normalised) ; v <- M_c^{-1} g.
+extern "C" int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, double rtol,
+                          double *lambda_max)
+{
+    NEED_BOUND(h);
+    if (!aligned(A) || !lambda_max || power_iters < 1 || !(rtol > 0))
+        return fail(h, EC_ERR_ARG, "bad arguments");
+    if (h->nc == 0) return fail(h, EC_ERR_ARG, "no conducting edges");
+    hipStream_t st = h->st;
+    std::vector<double> v(h->nc), gv(h->nc);
+    uint32_t s = 12345u;
+    for (int t = 0; t < h->nc; ++t) {
+        s = s * 1664525u + 1013904223u;
+        v[t] = (double)(s >> 8) / 16777216.0 - 0.5;
+    }
+    ec_solve_opts o{rtol, 1000000, EC_PREC_FP64, 0.0, 0, 0};
+    double lam = 0.0;
+    for (int it = 0; it < power_iters; ++it) {
+        double nrm = 0.0;
+        for (int t = 0; t < h->nc; ++t) nrm += v[t] * v[t] / h->minv[t];
+        nrm = std::sqrt(nrm);
+        for (int t = 0; t < h->nc; ++t) v[t] /= nrm;
+        HIP_TRY(h, hipMemcpyAsync(h->cvec_d, v.data(), (size_t)h->nc * 8, hipMemcpyHostToDevice, st));
+        fill(h->t4, 0.0, h->npad, st);
+        scatter_c(h->cslot_d, h->nc, h->cvec_d, h->t4, st);
+        fill(h->w, 0.0, h->npad, st);
+        spmv(h->g, h->t4, h->w, h->band_lo, h->band_hi, st);
+        int32_t rc = run_cg64(h, EC_SEQ_USER, START_ZERO, h->w, nullptr, h->t2, &o, nullptr);
+        if (rc) return rc;
+        // g = [K_nu(A) (v (+) -s)]_C with v on C (t4) and -s on N (t3)
+        negate(h->t2, h->t3, h->npad, st);
+        UpdArgs u{};
+        u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
+        u.nc = h->nc; u.A = h->t4; u.sj = nullptr; u.sc = nullptr; u.xn = h->t3;
+        u.nustate = A; u.apply = 1;
+        // g into t2's conducting slots (apply mode writes C entries only)
+        u.out = h->t2;
+        update_c(u, st);
+        gather_c(h->cslot_d, h->nc, h->t2, h->cvec_d, st);
+        HIP_TRY(h, hipMemcpyAsync(gv.data(), h->cvec_d, (size_t)h->nc * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(h, hipStreamSynchronize(st));
+        double num = 0.0;
+        for (int t = 0; t < h->nc; ++t) num += v[t] * gv[t];
+        lam = num;
+        for (int t = 0; t < h->nc; ++t) v[t] = gv[t] * h->minv[t];
+    }
+    *lambda_max = lam;
+    return launch_check(h, "cfl");
+}
+
+// ------------------------------------------------------------ graphs
+extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
+                                         const ec_step_opts *opts, ec_solve_info *dev_info,
+                                         void **graph_exec)
+{
+    NEED_BOUND(h);
+    int32_t rc = check_step_args(h, dt, A, opts);
+    if (rc) return rc;
+    if (!graph_exec) return fail(h, EC_ERR_ARG, "graph_exec is NULL");
+    // configure the histories eagerly so that no reset is recorded
+    for (int s : {EC_SEQ_SRC, EC_SEQ_CPL})
+        seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    rc = step_impl(h, -1, dt, A, opts, dev_info);
+    hipError_t e = hipStreamEndCapture(h->st, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(h, EC_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(h, EC_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+    *graph_exec = (void *)ex;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_graph_launch(void *graph_exec, void *hip_stream)
+{
+    if (!graph_exec) return fail(nullptr, EC_ERR_ARG, "graph_exec is NULL");
+    hipError_t e = hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    return EC_OK;
+}
+
+extern "C" int32_t ec_graph_destroy(void *graph_exec)
+{
+    if (graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+    return EC_OK;
+}
+
+extern "C" const char *ec_last_error(ec_handle h)
+{
+    return h ? h->err.c_str() : g_create_error.c_str();
+}

@@ -1,0 +1,144 @@
+// ec_device.h -- device helpers shared by the library's kernels: node
+// decoding, edge classification, wave/block reductions and the curl-curl
+// stencil of one grid node.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ec_internal.h"
+
+namespace ec {
+
+// flat node index -> (i, j, k); exact for < 2^25 nodes (see the 1e-7 guard:
+// a non-integer quotient is at least 1/(px*py) > 1e-7 away from the next one)
+__device__ __forceinline__ void decode(const Geo &g, int64_t n, int &i, int &j, int &k)
+{
+    const int64_t pxy = (int64_t)g.px * g.py;
+    k = (int)((double)n * (1.0 / (double)pxy) + 1e-7);
+    const int64_t rem = n - (int64_t)k * pxy;
+    j = (int)((double)rem * (1.0 / (double)g.px) + 1e-7);
+    i = (int)(rem - (int64_t)j * g.px);
+}
+
+// 0 Dirichlet/padding, 1 conducting, 2 nonconducting (Sec. II dof split)
+__device__ __forceinline__ int edge_cls(const Geo &g, int c, int i, int j, int k, int64_t n)
+{
+    if (c == 0) {
+        if (i >= g.nx || j <= 0 || j >= g.ny || k <= 0 || k >= g.nz) return 0;
+    } else if (c == 1) {
+        if (j >= g.ny || i <= 0 || i >= g.nx || k <= 0 || k >= g.nz) return 0;
+    } else {
+        if (k >= g.nz || i <= 0 || i >= g.nx || j <= 0 || j >= g.ny) return 0;
+    }
+    if (!g.box) return g.cls[(int64_t)c * g.S + n];
+    const int e0 = c == 0 ? 0 : 1, e1 = c == 1 ? 0 : 1, e2 = c == 2 ? 0 : 1;
+    const bool inC = i >= g.clo[0] && i <= g.chi[0] + e0 && j >= g.clo[1] &&
+                     j <= g.chi[1] + e1 && k >= g.clo[2] && k <= g.chi[2] + e2;
+    return inC ? 1 : 2;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NV values over a block of blockDim.x <= 1024 threads; every thread
+// gets the sums.  Fixed order: deterministic.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV])
+{
+    __shared__ double lds[NV][16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[q][wv] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[q][w];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+// Deterministic sum of NV partial values over nb blocks (part[b*stride+q]),
+// by the whole block; every thread gets the sums.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *part, int nb, int stride,
+                                                double (&out)[NV])
+{
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[q] += part[(int64_t)b * stride + q];
+    }
+    block_sum<NV>(out);
+}
+
+// K_air x at the three edges of node n: C^T M_nu0 C from the 24 edge values
+// around the node.  ld(c, idx) returns the (possibly transformed) input at
+// absolute index idx of direction block c.  The caller zeroes outputs on
+// edges that are not nonconducting.  Out-of-range neighbours (only ever used
+// by Dirichlet/padding outputs) are clamped into the array.
+template <typename T, typename LD>
+__device__ __forceinline__ void curlcurl_node(const Geo &g, int64_t n, LD ld, T &qx, T &qy,
+                                              T &qz)
+{
+    const int64_t oi = 1, oj = g.px, ok = (int64_t)g.px * g.py;
+    const int64_t S = g.S, S2 = 2 * g.S, last = 3 * g.S - 1;
+    auto X = [&](int64_t o) {
+        int64_t a = n + o;
+        a = a < 0 ? 0 : a;
+        return ld(0, a);
+    };
+    auto Y = [&](int64_t o) { return ld(1, S + n + o); };
+    auto Z = [&](int64_t o) {
+        int64_t a = S2 + n + o;
+        a = a > last ? last : a;
+        return ld(2, a);
+    };
+    const T x0 = X(0), x_kp = X(ok), x_km = X(-ok), x_im_kp = X(ok - oi), x_im = X(-oi),
+            x_jp = X(oj), x_jm = X(-oj), x_im_jp = X(oj - oi);
+    const T y0 = Y(0), y_kp = Y(ok), y_km = Y(-ok), y_jm = Y(-oj), y_jm_kp = Y(ok - oj),
+            y_ip = Y(oi), y_ip_jm = Y(oi - oj), y_im = Y(-oi);
+    const T z0 = Z(0), z_jp = Z(oj), z_jp_km = Z(oj - ok), z_km = Z(-ok), z_jm = Z(-oj),
+            z_ip = Z(oi), z_ip_km = Z(oi - ok), z_im = Z(-oi);
+    // face fluxes (right-handed circulation)
+    const T Fx = y0 + z_jp - y_kp - z0;                // x-face (i,j,k)
+    const T Fx_km = y_km + z_jp_km - y0 - z_km;        // x-face (i,j,k-1)
+    const T Fx_jm = y_jm + z0 - y_jm_kp - z_jm;        // x-face (i,j-1,k)
+    const T Fy = z0 + x_kp - z_ip - x0;                // y-face (i,j,k)
+    const T Fy_km = z_km + x0 - z_ip_km - x_km;        // y-face (i,j,k-1)
+    const T Fy_im = z_im + x_im_kp - z0 - x_im;        // y-face (i-1,j,k)
+    const T Fz = x0 + y_ip - x_jp - y0;                // z-face (i,j,k)
+    const T Fz_jm = x_jm + y_ip_jm - x0 - y_jm;        // z-face (i,j-1,k)
+    const T Fz_im = x_im + y0 - x_im_jp - y_im;        // z-face (i-1,j,k)
+    const T wx = (T)g.wx, wy = (T)g.wy, wz = (T)g.wz;
+    qx = wz * (Fz - Fz_jm) - wy * (Fy - Fy_km);
+    qy = wx * (Fx - Fx_km) - wz * (Fz - Fz_im);
+    qz = wy * (Fy - Fy_im) - wx * (Fx - Fx_jm);
+}
+
+// Tile loop of a node kernel: blocks b = 8*loc + xcd sweep the tiles of
+// XCD slab xcd (contiguous k-planes stay in that XCD's L2).  nb % 8 == 0.
+template <typename F>
+__device__ __forceinline__ void for_tiles(int tiles, int64_t S, F fn)
+{
+    const int nb = gridDim.x, xcd = blockIdx.x & 7, loc = blockIdx.x >> 3, nloc = nb >> 3;
+    const int tpx = (tiles + 7) >> 3;
+    for (int t = loc; t < tpx; t += nloc) {
+        const int tile = xcd * tpx + t;
+        if (tile >= tiles) break;
+        const int64_t n = (int64_t)tile * kTile + threadIdx.x;
+        if (n < S) fn(n);
+    }
+}
+
+}  // namespace ec

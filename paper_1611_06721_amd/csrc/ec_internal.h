@@ -1,0 +1,238 @@
+// ec_internal.h -- device-side data structures and kernel launchers of the
+// gfx950 library (private to the library; the public boundary is ec.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ec.h"
+
+namespace ec {
+
+constexpr int kMaxWin = EC_MAX_WINDOW + 4;   // columns of the small matrices
+                                             // (window + the column being added)
+constexpr int kMaxMat = 16;              // materials incl. id 0
+constexpr int kTile = 256;               // nodes per tile = threads per block
+constexpr int kMdBlocks = 256;           // grid of the basis-product kernels
+constexpr int kMdStride = 2 * kMaxWin;  // partial values per block
+constexpr int kMaxBlocks = 2048;        // grid cap of node kernels (multiple of 8)
+
+// Grid geometry and the constant-coefficient stencil of the nonconducting
+// region.  Every face touching a nonconducting edge lies between two
+// nonconducting cells, so K_n and K_cn^T use the single reluctivity nu0.
+struct Geo {
+    int nx, ny, nz;
+    int px, py;              // nx+1, ny+1 (node strides)
+    int64_t S;               // entries per direction block = node count
+    int64_t npad;            // 3*S
+    double hx, hy, hz;
+    double wx, wy, wz;       // nu0 * (dual length / area) of x/y/z-normal faces
+    double dinv[3];          // Jacobi: 1/diag(K_n) of x/y/z edges
+    int box;                 // conductor is an axis-aligned box of cells
+    int clo[3], chi[3];      // that box (cells, inclusive); clo > chi: none
+    const uint8_t *cls;      // edge classes when box == 0
+};
+
+// Materials: per id reluctivity coefficients and conductivity.
+struct Mats {
+    double sig[kMaxMat], k1[kMaxMat], k2[kMaxMat], k3[kMaxMat];
+    double nu0;
+    int n;
+};
+
+// Device-resident state of one right-hand-side sequence.
+//  SPE: Q columns (raw, orthogonal) with scales s_i (q_i = s_i Q_i), KQ the
+//       K_n products of the raw columns; H = q^T K q (normalised); R the
+//       window coordinates (X_window = q R, upper triangular k x k).
+//  POD: ring of raw snapshots X and K X; G = X^T X, H = X^T K X.
+struct SeqDev {
+    int method, cap, k, w;
+    int accept, rotate, active, flags;
+    int kpod, head, count, status;
+    int ncol_md;             // columns handed to the next basis product
+    int npush;               // POD: ring columns of the next push (incl. the new slot)
+    int zero_start;          // 1: the start vector is zero
+    int pad1;
+    double xnorm, rho, pod_info, r0_rel;
+    double pod_eps;
+    int pod_kmax, pad2;
+    double s[kMaxWin + 1];
+    double H[kMaxWin * kMaxWin];
+    double R[kMaxWin * kMaxWin];
+    double G[kMaxWin * kMaxWin];
+    double V[kMaxWin * kMaxWin];
+    double lam[kMaxWin];
+    double c1[kMaxWin + 1], c2[kMaxWin + 1];
+    double cA[kMaxWin + 1], cB[kMaxWin + 1];   // lincomb coefficients
+    double a1, a2;                              // lincomb scalars
+    double rot[kMaxWin * kMaxWin];              // basis rotation (SPE downdate)
+    int rot_in, rot_k;                          // columns in / kept by the rotation
+    int slot_new;                               // column slot being filled
+    int pad3;
+};
+
+// Per-handle control block in device memory.
+struct Ctrl {
+    int64_t step;            // step counter m
+    double scale;            // i_S(t_m) of the current step
+    double one;              // constant 1.0 (scale of unscaled right-hand sides)
+    double dt;
+    int64_t n_steps;
+    int64_t iters[EC_NSEQ];
+    int worst;               // most severe status seen (most negative)
+    int pad;
+    int refine_done;         // FP32-refined outer loop finished flag
+    int refine_zero;         // the right-hand side was zero
+    double refine_rr, refine_bb;
+};
+
+// ----------------------------------------------------------------- launchers
+struct Vec2 {
+    const double *p;
+    const double *scale;     // device scalar or nullptr (=1)
+};
+
+void spmv(const Geo &g, const double *x, double *y, const int lo[3], const int hi[3],
+          hipStream_t st);
+// y = K_n x over the full grid; if slot != nullptr also copy y to
+// ycopy + (*slot)*ld and x to xcopy + (*slot)*ld; skipped when *active == 0
+void spmv_slot(const Geo &g, const double *x, double *y, double *ycopy, double *xcopy,
+               const int *slot, int64_t ld, const int *active, hipStream_t st);
+void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st);
+
+// PCG start modes
+enum { START_ZERO = 0, START_X = 1, START_R = 2, START_DEV = 3, START_R2 = 4 };
+
+// Device control record of one CG solve, double buffered by kernel parity:
+// kernel i reads ctl[i & 1] and writes ctl[(i + 1) & 1].
+struct CgCtl {
+    double alpha, gamma, rho, bb, tol2, rho0, pad0, pad1;
+    int it, done, status, zero_x;
+    int pad2[4];
+};
+
+// Jacobi-PCG in the single-reduction form (Chronopoulos-Gear): one kernel
+// per iteration; r, w = K_n D^-1 r and s = K_n p double buffered.  Every
+// kernel reduces the block partials of the previous one (no atomics).
+template <typename T>
+struct CgArgs {
+    Geo g;
+    T *x, *p;
+    T *rb[2], *wb[2], *sb[2];
+    const T *b;
+    const double *bscale;    // device scalar multiplying b (nullptr: 1)
+    int mode;                // START_*
+    const SeqDev *seq;       // START_DEV reads seq->zero_start; basis info
+    double rtol;
+    int maxit;
+    CgCtl *ctl;              // [2]
+    double *part;            // [2][blocks][4]
+    ec_solve_info *info;     // may be nullptr
+    Ctrl *ctrl;              // accumulators (may be nullptr)
+    int seq_id;
+    int accum;               // add iterations to info->iters (inner refinement solves)
+    const int *skip;         // device flag: nonzero -> kernels return at once
+    int tiles;
+    int blocks;
+};
+
+template <typename T>
+void cg_init(const CgArgs<T> &a, hipStream_t st);
+template <typename T>
+void cg_iter(const CgArgs<T> &a, int i, hipStream_t st);
+template <typename T>
+void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st);
+
+// basis products  C = [A_0..A_{p-1}, a_extra]^T [B_0..B_{nb-1}]  (FP64 MFMA)
+struct MdArgs {
+    const double *A;
+    int64_t ld;
+    const int *kp;           // column count on device (nullptr: kfix)
+    int kfix;
+    const double *a_extra;
+    Vec2 B[4];
+    int nb;
+    const int *active;       // device flag (nullptr: always)
+    double *part;
+    int64_t n;
+};
+void multidot(const MdArgs &a, hipStream_t st);
+
+// y1 = a1 v1 + sum cA_i A_i ; y2 = a2 s2 v2 - ... (see kernel) with partial norms
+struct LcArgs {
+    const double *A, *B;
+    int64_t ld;
+    const int *kp;
+    const double *cA, *cB;
+    const double *a1, *a2;   // device scalars
+    const double *v1;
+    Vec2 v2;
+    double *y1, *y2;
+    const int *active;
+    const int *slot;         // if not null, y1 is column *slot of A
+    int want_dots;           // partial dots A_i^T y1 (i < k) and |y1|^2
+    double *part;
+    int64_t n;
+};
+void lincomb(const LcArgs &a, hipStream_t st);
+
+// in-place basis rotation: columns j < k' of A (and B) become sum_i rot[i,j] A_i
+void rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq, hipStream_t st);
+
+// dense steps on one sequence: one block reduces the partial rows of the
+// preceding basis product and runs the step
+enum {
+    OP_NONE = -1,
+    OP_SPE_START = 0,   // vals: Q_i^T b (k)
+    OP_SPE_PUSH1,       // vals: Q_i^T x (k), x^T x
+    OP_SPE_PUSH2,       // vals: Q_i^T w (k), |w|^2
+    OP_SPE_PUSH3,       // vals: |x2|^2
+    OP_SPE_PUSH4,       // vals: (KQ_i)^T x2, i <= k
+    OP_POD_PUSH,        // vals: X_i^T x_new, X_i^T K x_new  (pairs)
+    OP_POD_START,       // vals: X_i^T b (count)
+    OP_RESET
+};
+void small(SeqDev *seq, int op, const double *part, int nvals, double tol, ec_solve_info *info,
+           hipStream_t st);
+void seq_reset(SeqDev *seq, hipStream_t st);
+
+// nonlinear a_c update (eq. 6) / K_c + K_cn apply over conducting edges
+struct UpdArgs {
+    Geo g;
+    const Mats *m;           // device copy of the material table
+    const uint8_t *cmat;
+    const int *cslot;
+    const double *minv;      // 1/M_sigma per conducting edge
+    int nc;
+    const double *A;         // state: a_c read on C
+    const double *sj, *sc;   // y = sj - sc on N (sc may be nullptr)
+    const double *xn;        // alternative N operand (apply mode), may be nullptr
+    const double *nustate;   // state whose a_c sets nu (nullptr: the operand itself)
+    double *out;             // update: a_c^m on C; apply: g on C
+    double dt;
+    int apply;
+    const Ctrl *ctrl;
+};
+void update_c(const UpdArgs &a, hipStream_t st);
+
+void finish_state(const Geo &g, double *A, const double *ac, const double *sj,
+                  const double *sc, Ctrl *ctrl, int bump, hipStream_t st);
+void step_begin(Ctrl *ctrl, int64_t m, int wf, double amp, double freq, double tau,
+                int64_t ramp, double dt, hipStream_t st);
+void fill(double *y, double v, int64_t n, hipStream_t st);
+void copy_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
+void mask_copy(const Geo &g, const double *x, double *y, int cls_keep, hipStream_t st);
+// FP32-refined solve: r = b - K_n x in FP64 (and r32 = r) with block
+// partials; refine_decide (one block) reduces them and sets ctrl->refine_done
+void refine_residual(const Geo &g, const double *b, const double *bscale, const double *x,
+                     float *r32, double *part, const Ctrl *ctrl, int blocks, hipStream_t st);
+void refine_decide(const double *part, int blocks, Ctrl *ctrl, int pass, int outer_max,
+                   double rtol, ec_solve_info *info, const SeqDev *seq, hipStream_t st);
+void refine_update(double *x, const float *d, const Ctrl *ctrl, int64_t n, hipStream_t st);
+void refine_final(double *x, const Ctrl *ctrl, int64_t n, hipStream_t st);
+void refine_reset(Ctrl *ctrl, hipStream_t st);
+void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st);
+void negate(const double *x, double *y, int64_t n, hipStream_t st);
+void gather_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
+void scatter_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
+
+}  // namespace ec

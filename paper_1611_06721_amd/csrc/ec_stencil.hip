@@ -1,0 +1,508 @@
+// ec_stencil.hip -- curl-curl products and the Jacobi-PCG for the
+// pseudo-inverse K_n^+ b of eq. (9) on gfx950.
+//
+// SpMV: y = [K_air x]_N, matrix free (K_n x for x on nonconducting edges,
+// K_cn^T x for x on conducting edges; eq. 3 blocks), one thread per node.
+//
+// PCG (Sec. III; weak gauging of Sec. II): the single-reduction form of
+// Jacobi-preconditioned CG (Chronopoulos and Gear), algebraically the same
+// iterates as standard PCG.  With u = D^-1 r, w = K_n u:
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}     (s = K_n p)
+//   x += alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,  w_{i+1} = K_n D^-1 r_{i+1}
+//   gamma = r^T u, delta = w^T u:  beta_{i+1} = gamma_{i+1}/gamma_i,
+//   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1}/alpha_i)
+// One kernel per iteration computes r_{i+1} at the 24 stencil points on the
+// fly, so the iteration needs a single grid-wide reduction.  Each kernel
+// starts by reducing the previous kernel's block partials (every block, same
+// order: no atomics or cache flushes) and derives alpha, beta and the stop
+// decision.  Stop: ||r|| <= rtol ||b|| (recursive residual).
+#include <math.h>
+
+#include "ec_device.h"
+
+namespace ec {
+
+// ------------------------------------------------------------- SpMV kernel
+// Blocks are mapped XCD-contiguously (block b runs on XCD b % 8): each XCD
+// sweeps one slab, so the k +- 1 planes of the stencil stay in its own L2.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_spmv(Geo g, const T *__restrict__ x, T *__restrict__ y, int lo0, int lo1, int lo2,
+           int ex, int ey, int ez, int tiles, int tpx, T *__restrict__ ycopy,
+           T *__restrict__ xcopy, const int *slot, int64_t ld, const int *active)
+{
+    if (active && !*active) return;
+    const int b = blockIdx.x, tile = (b & 7) * tpx + (b >> 3);
+    if (tile >= tiles) return;
+    const int64_t t = (int64_t)tile * kTile + threadIdx.x;
+    const int64_t cnt = (int64_t)ex * ey * ez;
+    if (t >= cnt) return;
+    if (slot) {
+        if (ycopy) ycopy += (int64_t)(*slot) * ld;
+        if (xcopy) xcopy += (int64_t)(*slot) * ld;
+    }
+    const int64_t exy = (int64_t)ex * ey;
+    const int kk = (int)((double)t * (1.0 / (double)exy) + 1e-7);
+    const int64_t rem = t - (int64_t)kk * exy;
+    const int jj = (int)((double)rem * (1.0 / (double)ex) + 1e-7);
+    const int ii = (int)(rem - (int64_t)jj * ex);
+    const int i = ii + lo0, j = jj + lo1, k = kk + lo2;
+    const int64_t n = ((int64_t)k * g.py + j) * g.px + i;
+    T q[3];
+    curlcurl_node<T>(g, n, [&](int, int64_t a) { return x[a]; }, q[0], q[1], q[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t ix = (int64_t)c * g.S + n;
+        const T v = edge_cls(g, c, i, j, k, n) == 2 ? q[c] : (T)0;
+        y[ix] = v;
+        if (ycopy) ycopy[ix] = v;
+        if (xcopy) xcopy[ix] = x[ix];
+    }
+}
+
+template <typename T>
+static void spmv_launch_box(const Geo &g, const T *x, T *y, const int lo[3], const int ext[3],
+                            hipStream_t st, T *ycopy, T *xcopy, const int *slot, int64_t ld,
+                            const int *active)
+{
+    const int64_t cnt = (int64_t)ext[0] * ext[1] * ext[2];
+    if (cnt <= 0) return;
+    const int tiles = (int)((cnt + kTile - 1) / kTile);
+    const int tpx = (tiles + 7) / 8;
+    hipLaunchKernelGGL(k_spmv<T>, dim3(8 * tpx), dim3(kTile), 0, st, g, x, y, lo[0], lo[1],
+                       lo[2], ext[0], ext[1], ext[2], tiles, tpx, ycopy, xcopy, slot, ld, active);
+}
+
+void spmv(const Geo &g, const double *x, double *y, const int lo[3], const int hi[3],
+          hipStream_t st)
+{
+    const int ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+    spmv_launch_box<double>(g, x, y, lo, ext, st, nullptr, nullptr, nullptr, 0, nullptr);
+}
+
+void spmv_slot(const Geo &g, const double *x, double *y, double *ycopy, double *xcopy,
+               const int *slot, int64_t ld, const int *active, hipStream_t st)
+{
+    const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
+    spmv_launch_box<double>(g, x, y, lo, ext, st, ycopy, xcopy, slot, ld, active);
+}
+
+void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st)
+{
+    const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
+    spmv_launch_box<float>(g, x, y, lo, ext, st, nullptr, nullptr, nullptr, 0, nullptr);
+}
+
+// ------------------------------------------------------------------- CG
+__device__ __forceinline__ double dsel(const double (&d)[3], int c)
+{
+    return c == 0 ? d[0] : (c == 1 ? d[1] : d[2]);
+}
+
+// Reduce the [blocks][4] partials of the previous kernel (every block, same
+// fixed order: every block obtains bitwise the same sums).
+__device__ __forceinline__ void sum_part(const double *P, int nb, double (&t)[4])
+{
+    reduce_partials<4>(P, nb, 4, t);
+}
+
+// Init, phase START_X: r0 = s b - K_n x0, partials (|r0|^2, |b|^2) into part[1].
+// Init, phases ZERO / R / R2 / DEV: w0 = K_n D^-1 r0 and partials
+// (gamma0 = r0^T D^-1 r0, delta0 = w0^T D^-1 r0, |r0|^2, |b|^2) into part[0].
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
+{
+    if (a.skip && *a.skip) return;
+    const Geo &g = a.g;
+    const int64_t S = g.S;
+    const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
+    const double bs = a.bscale ? *a.bscale : 1.0;
+    int mode = a.mode;
+    if (mode == START_DEV) mode = a.seq->zero_start ? START_ZERO : START_R;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    T *r0 = a.rb[0];
+    double *P0 = a.part, *P1 = a.part + 4 * (int64_t)kMaxBlocks;
+    if (mode == START_X) {
+        for_tiles(a.tiles, S, [&](int64_t n) {
+            int i, j, k;
+            decode(g, n, i, j, k);
+            T q[3];
+            curlcurl_node<T>(g, n, [&](int, int64_t ix) { return a.x[ix]; }, q[0], q[1], q[2]);
+            for (int c = 0; c < 3; ++c) {
+                const int64_t ix = c * S + n;
+                const double kx = edge_cls(g, c, i, j, k, n) == 2 ? (double)q[c] : 0.0;
+                const double bv = bs * (double)a.b[ix];
+                const T rv = (T)(bv - kx);
+                r0[ix] = rv;
+                v[0] += (double)rv * (double)rv;
+                v[1] += bv * bv;
+            }
+        });
+        block_sum<4>(v);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 4; ++q) P1[(int64_t)blockIdx.x * 4 + q] = v[q];
+        return;
+    }
+    bool zero_all = false;
+    if (mode == START_R2) {
+        double t[4];
+        sum_part(P1, gridDim.x, t);
+        zero_all = t[1] == 0.0;   // b = 0: the pseudo-inverse solution is x = 0
+    }
+    for_tiles(a.tiles, S, [&](int64_t n) {
+        int i, j, k;
+        decode(g, n, i, j, k);
+        T w[3] = {(T)0, (T)0, (T)0};
+        if (zero_all) {
+            for (int c = 0; c < 3; ++c) {
+                a.x[c * S + n] = (T)0;
+                r0[c * S + n] = (T)0;
+                a.wb[0][c * S + n] = (T)0;
+            }
+            return;
+        }
+        if (mode == START_ZERO) {
+            const T tbs = (T)bs;
+            curlcurl_node<T>(
+                g, n, [&](int c, int64_t ix) { return (T)dsel(dd, c) * (tbs * a.b[ix]); }, w[0],
+                w[1], w[2]);
+        } else {
+            curlcurl_node<T>(g, n, [&](int c, int64_t ix) { return (T)dsel(dd, c) * r0[ix]; },
+                             w[0], w[1], w[2]);
+        }
+        for (int c = 0; c < 3; ++c) {
+            const int64_t ix = c * S + n;
+            if (edge_cls(g, c, i, j, k, n) != 2) w[c] = (T)0;
+            const double bv = bs * (double)a.b[ix];
+            double rv;
+            if (mode == START_ZERO) {
+                r0[ix] = (T)bv;
+                a.x[ix] = (T)0;
+                rv = (double)(T)bv;
+            } else {
+                rv = (double)r0[ix];
+            }
+            a.wb[0][ix] = w[c];
+            const double u = dd[c] * rv;
+            v[0] += u * rv;
+            v[1] += (double)w[c] * u;
+            v[2] += rv * rv;
+            v[3] += bv * bv;
+        }
+    });
+    block_sum<4>(v);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 4; ++q) P0[(int64_t)blockIdx.x * 4 + q] = v[q];
+        if (blockIdx.x == 0) {
+            CgCtl c0{};
+            c0.done = 0;
+            c0.status = EC_OK;
+            c0.zero_x = zero_all;
+            a.ctl[0] = c0;
+        }
+    }
+}
+
+// State entering kernel i from the reduced partials t = (gamma, delta, rho,
+// bb) of the previous kernel and its record prev.  Same in every block.
+__device__ __forceinline__ CgCtl cg_state(const CgCtl &prev, const double (&t)[4], int i,
+                                          double rtol, int maxit, double &beta)
+{
+    CgCtl c = prev;
+    beta = 0.0;
+    if (prev.done) return c;
+    const double gam = t[0], del = t[1], rho = t[2];
+    double den;
+    if (i == 0) {
+        c.bb = t[3];
+        c.tol2 = rtol * rtol * c.bb;
+        c.rho0 = rho;
+        den = del;
+    } else {
+        beta = gam / prev.gamma;
+        den = del - beta * gam / prev.alpha;
+    }
+    c.gamma = gam;
+    c.rho = rho;
+    c.alpha = gam / den;
+    c.it = i;
+    c.status = EC_OK;
+    if (!(rho == rho) || rho > 1e300) {
+        c.done = 1;
+        c.status = EC_ERR_NONFINITE;
+    } else if (c.bb == 0.0 || rho <= c.tol2) {
+        c.done = 1;
+    } else if (i >= maxit) {
+        c.done = 1;
+        c.status = EC_ERR_NOT_CONVERGED;
+    } else if (!(den > 0.0) || !(gam > 0.0)) {
+        c.done = 1;
+        c.status = EC_ERR_BREAKDOWN;
+    }
+    return c;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
+{
+    if (a.skip && *a.skip) return;
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;
+    double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
+    {
+        double t[4];
+        sum_part(Pin, gridDim.x, t);
+        if (threadIdx.x == 0) {
+            double beta;
+            s_c = cg_state(a.ctl[it & 1], t, it, a.rtol, a.maxit, beta);
+            s_beta = beta;
+            if (blockIdx.x == 0) {
+                CgCtl o = s_c;
+                if (!o.done) o.it = it + 1;   // iterations completed after this kernel
+                a.ctl[(it + 1) & 1] = o;
+            }
+        }
+        __syncthreads();
+    }
+    if (s_c.done) return;
+    const Geo &g = a.g;
+    const int64_t S = g.S;
+    const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
+    const double alpha = s_c.alpha, beta = s_beta;
+    const T ta = (T)alpha, tb = (T)beta;
+    const T *rc = a.rb[it & 1], *wc = a.wb[it & 1], *sp = a.sb[(it + 1) & 1];
+    T *rn = a.rb[(it + 1) & 1], *wn = a.wb[(it + 1) & 1], *sc = a.sb[it & 1];
+    const bool first = it == 0;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for_tiles(a.tiles, S, [&](int64_t n) {
+        int i, j, k;
+        decode(g, n, i, j, k);
+        T w[3];
+        if (first) {
+            curlcurl_node<T>(
+                g, n, [&](int c, int64_t ix) { return (T)dsel(dd, c) * (rc[ix] - ta * wc[ix]); },
+                w[0], w[1], w[2]);
+        } else {
+            curlcurl_node<T>(
+                g, n,
+                [&](int c, int64_t ix) {
+                    return (T)dsel(dd, c) * (rc[ix] - ta * (wc[ix] + tb * sp[ix]));
+                },
+                w[0], w[1], w[2]);
+        }
+        for (int c = 0; c < 3; ++c) {
+            const int64_t ix = c * S + n;
+            const T d = (T)dsel(dd, c);
+            const T rv = rc[ix], wv = wc[ix];
+            const T si = first ? wv : wv + tb * sp[ix];
+            const T pi = first ? d * rv : d * rv + tb * a.p[ix];
+            a.x[ix] += ta * pi;
+            a.p[ix] = pi;
+            sc[ix] = si;
+            const T r1 = rv - ta * si;
+            rn[ix] = r1;
+            const T w1 = edge_cls(g, c, i, j, k, n) == 2 ? w[c] : (T)0;
+            wn[ix] = w1;
+            const double u1 = (double)d * (double)r1;
+            v[0] += u1 * (double)r1;
+            v[1] += (double)w1 * u1;
+            v[2] += (double)r1 * (double)r1;
+        }
+    });
+    block_sum<4>(v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) Pout[(int64_t)blockIdx.x * 4 + q] = v[q];
+}
+
+// After `iters` iteration kernels: final decision on the last iterate, the
+// solve record and the per-sequence counters (one block).
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_fin(CgArgs<T> a, int iters)
+{
+    if (a.skip && *a.skip) return;
+    double t[4];
+    sum_part(a.part + (int64_t)(iters & 1) * 4 * kMaxBlocks, a.blocks, t);
+    if (threadIdx.x != 0) return;
+    double beta;
+    // maxit + 1 lets the last iterate be judged on its residual only
+    CgCtl c = cg_state(a.ctl[iters & 1], t, iters, a.rtol, a.maxit + 1, beta);
+    int st = c.status;
+    if (!c.done) st = EC_ERR_NOT_CONVERGED;
+    const int it = c.it;
+    if (a.info) {
+        if (a.accum) {
+            a.info->iters += it;
+        } else {
+            const double bb = c.bb;
+            a.info->iters = it;
+            a.info->outer_iters = 0;
+            a.info->rel_res = bb > 0.0 ? sqrt(c.rho / bb) : 0.0;
+            a.info->b_norm = sqrt(bb);
+            a.info->r0_rel = bb > 0.0 ? sqrt(c.rho0 / bb) : 0.0;
+            int s2 = st;
+            if (a.seq) {
+                a.info->basis_cols = a.seq->method == EC_SV_POD ? a.seq->kpod : a.seq->k;
+                a.info->pod_info = a.seq->method == EC_SV_POD ? a.seq->pod_info : 1.0;
+                if (s2 == EC_OK && a.seq->flags) s2 = EC_ERR_SINGULAR_PROJ;
+            } else {
+                a.info->basis_cols = 0;
+                a.info->pod_info = 1.0;
+            }
+            a.info->status = s2;
+        }
+    }
+    if (a.ctrl) {
+        a.ctrl->iters[a.seq_id] += it;
+        if (st < a.ctrl->worst) a.ctrl->worst = st;
+    }
+}
+
+template <typename T>
+void cg_init(const CgArgs<T> &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(a.blocks), dim3(kTile), 0, st, a);
+}
+template <typename T>
+void cg_iter(const CgArgs<T> &a, int i, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_iter<T>, dim3(a.blocks), dim3(kTile), 0, st, a, i);
+}
+template <typename T>
+void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_fin<T>, dim3(1), dim3(256), 0, st, a, iters);
+}
+template void cg_init<double>(const CgArgs<double> &, hipStream_t);
+template void cg_iter<double>(const CgArgs<double> &, int, hipStream_t);
+template void cg_fin<double>(const CgArgs<double> &, int, hipStream_t);
+template void cg_init<float>(const CgArgs<float> &, hipStream_t);
+template void cg_iter<float>(const CgArgs<float> &, int, hipStream_t);
+template void cg_fin<float>(const CgArgs<float> &, int, hipStream_t);
+
+// --------------------------------------------------- FP32-refined solves
+// r = s b - K_n x in FP64, r32 = r, partials (|r|^2, |b|^2).
+__global__ void __launch_bounds__(256)
+    k_refine_resid(Geo g, const double *b, const double *bscale, const double *x, float *r32,
+                   double *part, const Ctrl *ctrl, int tiles)
+{
+    if (ctrl->refine_done) return;
+    const int64_t S = g.S;
+    const double bs = bscale ? *bscale : 1.0;
+    double v[2] = {0.0, 0.0};
+    for_tiles(tiles, S, [&](int64_t n) {
+        int i, j, k;
+        decode(g, n, i, j, k);
+        double q[3];
+        curlcurl_node<double>(g, n, [&](int, int64_t ix) { return x[ix]; }, q[0], q[1], q[2]);
+        for (int c = 0; c < 3; ++c) {
+            const int64_t ix = (int64_t)c * S + n;
+            const double kx = edge_cls(g, c, i, j, k, n) == 2 ? q[c] : 0.0;
+            const double bv = bs * b[ix];
+            const double rv = bv - kx;
+            r32[ix] = (float)rv;
+            v[0] += rv * rv;
+            v[1] += bv * bv;
+        }
+    });
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+void refine_residual(const Geo &g, const double *b, const double *bscale, const double *x,
+                     float *r32, double *part, const Ctrl *ctrl, int blocks, hipStream_t st)
+{
+    const int tiles = (int)((g.S + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_refine_resid, dim3(blocks), dim3(kTile), 0, st, g, b, bscale, x, r32, part,
+                       ctrl, tiles);
+}
+
+// Converged (||r|| <= rtol ||b||), out of passes, or another inner solve.
+__global__ void __launch_bounds__(256)
+    k_refine_decide(const double *part, int nb, Ctrl *ctrl, int pass, int outer_max, double rtol,
+                    ec_solve_info *info, const SeqDev *seq)
+{
+    if (ctrl->refine_done) return;
+    double s[2];
+    reduce_partials<2>(part, nb, 2, s);
+    if (threadIdx.x != 0) return;
+    const double rr = s[0], bb2 = s[1];
+    const double rel = bb2 > 0.0 ? sqrt(rr / bb2) : 0.0;
+    int done = 0, st = EC_OK;
+    if (!(rr == rr) || rr > 1e300) {
+        done = 1;
+        st = EC_ERR_NONFINITE;
+    } else if (bb2 == 0.0 || rel <= rtol) {
+        done = 1;
+    } else if (pass >= outer_max) {
+        done = 1;
+        st = EC_ERR_NOT_CONVERGED;
+    }
+    if (pass == 0 && info) {
+        info->iters = 0;
+        info->b_norm = sqrt(bb2);
+        info->r0_rel = rel;
+        info->basis_cols = seq ? (seq->method == EC_SV_POD ? seq->kpod : seq->k) : 0;
+        info->pod_info = (seq && seq->method == EC_SV_POD) ? seq->pod_info : 1.0;
+    }
+    if (done) {
+        ctrl->refine_done = 1;
+        ctrl->refine_zero = (bb2 == 0.0) ? 1 : 0;
+        if (info) {
+            info->outer_iters = pass;
+            info->rel_res = rel;
+            int s2 = st;
+            if (s2 == EC_OK && seq && seq->flags) s2 = EC_ERR_SINGULAR_PROJ;
+            info->status = s2;
+        }
+        if (st < ctrl->worst) ctrl->worst = st;
+    }
+    ctrl->refine_rr = rr;
+    ctrl->refine_bb = bb2;
+}
+
+void refine_decide(const double *part, int blocks, Ctrl *ctrl, int pass, int outer_max,
+                   double rtol, ec_solve_info *info, const SeqDev *seq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refine_decide, dim3(1), dim3(256), 0, st, part, blocks, ctrl, pass,
+                       outer_max, rtol, info, seq);
+}
+
+// x += d (FP32 correction) unless the loop has finished; b = 0 gives x = 0
+__global__ void k_refine_update(double *x, const float *d, const Ctrl *ctrl, int64_t n, int final)
+{
+    const int zero = ctrl->refine_zero;
+    if (final ? !zero : ctrl->refine_done) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        x[e] = final ? 0.0 : x[e] + (double)d[e];
+}
+
+void refine_update(double *x, const float *d, const Ctrl *ctrl, int64_t n, hipStream_t st)
+{
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_refine_update, dim3(blocks), dim3(256), 0, st, x, d, ctrl, n, 0);
+}
+
+void refine_final(double *x, const Ctrl *ctrl, int64_t n, hipStream_t st)
+{
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_refine_update, dim3(blocks), dim3(256), 0, st, x, (const float *)nullptr,
+                       ctrl, n, 1);
+}
+
+__global__ void k_refine_reset(Ctrl *ctrl)
+{
+    ctrl->refine_done = 0;
+    ctrl->refine_zero = 0;
+}
+
+void refine_reset(Ctrl *ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refine_reset, dim3(1), dim3(1), 0, st, ctrl);
+}
+
+}  // namespace ec

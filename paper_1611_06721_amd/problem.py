@@ -1,0 +1,205 @@
+"""torch-facing wrapper of the C-ABI: device memory and streams come from torch,
+every operation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import contextlib
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+INFO_BYTES = C.sizeof(L.SolveInfo)
+_INFO_DTYPE = np.dtype([("iters", "<i4"), ("outer_iters", "<i4"), ("status", "<i4"),
+                        ("basis_cols", "<i4"), ("rel_res", "<f8"), ("b_norm", "<f8"),
+                        ("pod_info", "<f8"), ("r0_rel", "<f8")])
+assert _INFO_DTYPE.itemsize == INFO_BYTES
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def solve_opts(rtol=1e-8, maxit=100000, precision=L.PREC_FP64, inner_rtol=1e-5,
+               inner_maxit=200, outer_max=8):
+    return L.SolveOpts(rtol, maxit, precision, inner_rtol, inner_maxit, outer_max)
+
+
+def step_opts(method=L.SV_SPE, window=8, pod_kmax=None, pod_eps=1e-4, **solve):
+    kmax = window if pod_kmax is None else pod_kmax
+    return L.StepOpts(method, window, kmax, pod_eps, solve_opts(**solve))
+
+
+def info_array(info_tensor):
+    """Device info records -> numpy structured array (synchronises)."""
+    raw = info_tensor.detach().cpu().numpy().view(np.uint8)
+    return raw.view(_INFO_DTYPE)
+
+
+class Problem:
+    """One FIT eddy-current problem bound to a torch device and stream.
+
+    `wl` is any object with the fields of synth.Workload (n, length, cell_mat,
+    materials, edge_current, waveform, amp, freq, tau, ramp_steps, nu0).
+
+    The library runs on its own (capturable, non-default) torch stream; every
+    call first waits for the caller's current stream and makes the caller's
+    stream wait for the library's work, so tensors can be used as usual."""
+
+    def __init__(self, wl, window_cap=8, device="cuda:0", stream=None):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        grid = L.Grid((C.c_int32 * 3)(*wl.n), (C.c_double * 3)(*wl.length))
+        self._cell = np.ascontiguousarray(wl.cell_mat, dtype=np.uint8)
+        mats = (L.Material * max(1, len(wl.materials)))(
+            *[L.Material(m.sigma, m.k1, m.k2, m.k3) for m in wl.materials])
+        mdesc = L.Materials(self._cell.ctypes.data_as(C.POINTER(C.c_uint8)), mats,
+                            len(wl.materials), wl.nu0)
+        self._xs = np.ascontiguousarray(wl.edge_current, dtype=np.float64)
+        src = L.Source(self._xs.ctypes.data_as(C.POINTER(C.c_double)), wl.waveform, wl.amp,
+                       wl.freq, wl.tau, int(wl.ramp_steps))
+        h = C.c_void_p()
+        L.check(self.lib.ec_create(C.byref(grid), C.byref(mdesc), C.byref(src), C.byref(h)))
+        self.h = h
+        npad, nc, nn, ws = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._chk(self.lib.ec_sizes(self.h, window_cap, C.byref(npad), C.byref(nc),
+                                    C.byref(nn), C.byref(ws)))
+        self.n_pad, self.n_c, self.n_n = npad.value, nc.value, nn.value
+        self.window_cap = window_cap
+        self.workspace = torch.empty(ws.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        with self._on_stream():
+            self._chk(self.lib.ec_bind(self.h, C.c_void_p(self.stream.cuda_stream),
+                                       C.c_void_p(self._ws_ptr), ws.value, window_cap))
+        self.wl = wl
+
+    # ------------------------------------------------------------ helpers
+    def _chk(self, code):
+        return L.check(code, self.h)
+
+    @contextlib.contextmanager
+    def _on_stream(self):
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+        try:
+            yield
+        finally:
+            if cur.cuda_stream != self.stream.cuda_stream:
+                cur.wait_stream(self.stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and getattr(self, "lib", None) is not None:
+            self.lib.ec_destroy(h)
+            self.h = None
+
+    def zeros(self):
+        return torch.zeros(self.n_pad, dtype=torch.float64, device=self.device)
+
+    def tensor(self, a):
+        return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
+
+    def info(self, n=1):
+        return torch.zeros(n * INFO_BYTES, dtype=torch.uint8, device=self.device)
+
+    # ------------------------------------------------------------ calls
+    def apply(self, op, x, out=None):
+        y = self.zeros() if out is None else out
+        with self._on_stream():
+            self._chk(self.lib.ec_apply(self.h, op, _ptr(x), _ptr(y)))
+        return y
+
+    def solve(self, b, x=None, seq=L.SEQ_USER, method=L.SV_ZERO, window=1, info=None, **opts):
+        x = self.zeros() if x is None else x
+        o = solve_opts(**opts)
+        with self._on_stream():
+            self._chk(self.lib.ec_solve(self.h, seq, method, window, _ptr(b), _ptr(x),
+                                        C.byref(o), _ptr(info)))
+        return x
+
+    def history_reset(self, seq):
+        with self._on_stream():
+            self._chk(self.lib.ec_history_reset(self.h, seq))
+
+    def history_push(self, seq, method, window, x):
+        with self._on_stream():
+            self._chk(self.lib.ec_history_push(self.h, seq, method, window, _ptr(x)))
+
+    def start_vector(self, seq, method, window, b, pod_kmax=None, pod_eps=1e-4, x0=None,
+                     info=None):
+        x0 = self.zeros() if x0 is None else x0
+        kmax = window if pod_kmax is None else pod_kmax
+        with self._on_stream():
+            self._chk(self.lib.ec_start_vector(self.h, seq, method, window, kmax, pod_eps,
+                                               _ptr(b), _ptr(x0), _ptr(info)))
+        return x0
+
+    def set_state(self, A, **opts):
+        o = solve_opts(**opts)
+        with self._on_stream():
+            self._chk(self.lib.ec_set_state(self.h, _ptr(A), C.byref(o)))
+
+    def step(self, A, m, dt, opts, info=None):
+        with self._on_stream():
+            self._chk(self.lib.ec_step(self.h, m, dt, _ptr(A), C.byref(opts), _ptr(info)))
+
+    def run(self, A, m0, nsteps, dt, opts, info=None):
+        with self._on_stream():
+            self._chk(self.lib.ec_run(self.h, m0, nsteps, dt, _ptr(A), C.byref(opts),
+                                      _ptr(info)))
+
+    def counters(self):
+        v = [C.c_int64() for _ in range(4)]
+        w = C.c_int32()
+        with self._on_stream():
+            self._chk(self.lib.ec_counters(self.h, *[C.byref(x) for x in v], C.byref(w)))
+        return {"steps": v[0].value, "iters_src": v[1].value, "iters_cpl": v[2].value,
+                "iters_adj": v[3].value, "worst_status": w.value}
+
+    def counters_reset(self):
+        with self._on_stream():
+            self._chk(self.lib.ec_counters_reset(self.h))
+
+    def set_step(self, m):
+        with self._on_stream():
+            self._chk(self.lib.ec_set_step(self.h, m))
+
+    def cfl(self, A=None, iters=60, rtol=1e-12):
+        A = self.zeros() if A is None else A
+        lam = C.c_double()
+        with self._on_stream():
+            self._chk(self.lib.ec_cfl(self.h, _ptr(A), iters, rtol, C.byref(lam)))
+        return lam.value
+
+    def graph_capture(self, A, dt, opts, info=None):
+        g = C.c_void_p()
+        with self._on_stream():
+            self._chk(self.lib.ec_graph_capture_step(self.h, dt, _ptr(A), C.byref(opts),
+                                                     _ptr(info), C.byref(g)))
+        return Graph(self, g)
+
+
+class Graph:
+    """A captured step; launch() replays it on the problem's stream."""
+
+    def __init__(self, prob, g):
+        self.prob, self.lib, self.g = prob, prob.lib, g
+
+    def launch(self):
+        with self.prob._on_stream():
+            L.check(self.lib.ec_graph_launch(self.g, C.c_void_p(self.prob.stream.cuda_stream)))
+
+    def launch_raw(self):
+        """Replay without stream hand-offs (the caller synchronises)."""
+        L.check(self.lib.ec_graph_launch(self.g, C.c_void_p(self.prob.stream.cuda_stream)))
+
+    def __del__(self):
+        if getattr(self, "g", None):
+            self.lib.ec_graph_destroy(self.g)
+            self.g = None

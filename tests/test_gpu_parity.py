@@ -1,0 +1,341 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Inputs are seeded (synth); expected values come from the oracle only.
+Tolerances: FP64 operator products agree to rounding (1e-13 relative to the
+largest entry); solves and trajectories at rtol 1e-12 agree to 1e-10 relative
+(the bound stated for the FP64 path); start vectors to 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.conftest import small_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ec():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1611_06721_amd as ec
+    return ec
+
+
+def lshape_workload():
+    """Non-box conductor (two overlapping boxes): exercises the class table."""
+    wl = small_workload(n=(9, 8, 7), length=(1.0, 0.9, 0.7), lo=(3, 3, 2), hi=(5, 4, 3))
+    cm = wl.cell_mat.reshape(7, 8, 9)
+    cm[4, 3:5, 3:6] = 1          # extend the box upwards
+    cm[2:5, 5, 3] = 1
+    wl.cell_mat = cm.reshape(-1).copy()
+    return wl
+
+
+def nonlinear16():
+    """Iron driven to ~2 T within 60 steps, still stable at half the bound."""
+    return synth.nonlinear(16, ramp_steps=40, J0=6.0e6)
+
+
+WORKLOADS = {
+    "c1": lambda: synth.linear_c1(12),
+    "small": lambda: small_workload(),
+    "lshape": lshape_workload,
+    "nl16": nonlinear16,
+}
+
+
+def pair(ec, oracle_mod, name, cap=8):
+    wl = WORKLOADS[name]()
+    return ec.Problem(wl, window_cap=cap), oracle_mod.Problem(wl), wl
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ------------------------------------------------------------ operators
+@pytest.mark.parametrize("name", ["c1", "small", "lshape", "nl16"])
+def test_kn_and_kcnT(ec, oracle_mod, name):
+    G, O, _ = pair(ec, oracle_mod, name)
+    for seed in (1, 2):
+        x = synth.random_vector(O.n_pad, O.N, seed)
+        y = G.apply(ec.OP_KN, G.tensor(x)).cpu().numpy()
+        assert rel(y, O.kn(x)) < 1e-13
+        a = synth.random_vector(O.n_pad, O.C, seed + 10)
+        y = G.apply(ec.OP_KCN_T, G.tensor(a)).cpu().numpy()
+        assert rel(y, O.kcnT(a)) < 1e-13
+        # a full random vector: the operators read only their own block
+        z = synth.random_vector(O.n_pad, ~O.D, seed + 20)
+        y = G.apply(ec.OP_KN, G.tensor(z)).cpu().numpy()
+        assert rel(y, O.kn(np.where(O.N, z, 0.0))) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["c1", "lshape", "nl16"])
+def test_kc_kcn_nonlinear(ec, oracle_mod, name):
+    """[K_nu(a) a]_C with the Brauer reluctivity evaluated at a (|B| ~ 1 T)."""
+    G, O, wl = pair(ec, oracle_mod, name)
+    rng = np.random.default_rng(5)
+    a = synth.random_vector(O.n_pad, ~O.D, 7)
+    h = min(wl.h)
+    a *= 0.4 * h * h / np.abs(a).max()       # |B| of order 1 T
+    y = G.apply(ec.OP_KC_KCN, G.tensor(a)).cpu().numpy()
+    ref = np.where(O.C, O.apply(a, a), 0.0)
+    assert rel(y, ref) < 1e-12
+
+
+def test_full_size_spmv(ec, oracle_mod):
+    """K_n at the 48^3 and 128^3 sizes, full comparison."""
+    for N in (48, 128):
+        wl = synth.nonlinear(N)
+        G = ec.Problem(wl, window_cap=1)
+        O = oracle_mod.Problem(wl)
+        x = synth.random_vector(O.n_pad, O.N, N)
+        y = G.apply(ec.OP_KN, G.tensor(x)).cpu().numpy()
+        assert rel(y, O.kn(x)) < 1e-13
+        del G
+
+
+# --------------------------------------------------------------- solves
+@pytest.mark.parametrize("name", ["c1", "small", "lshape"])
+def test_solve_zero_start(ec, oracle_mod, name):
+    G, O, _ = pair(ec, oracle_mod, name)
+    b = O.kcnT(synth.random_vector(O.n_pad, O.C, 3)) + O.source(2, 1e-3)
+    info = G.info(1)
+    x = G.solve(G.tensor(b), method=ec.SV_ZERO, rtol=1e-12, info=info).cpu().numpy()
+    I = ec.info_array(info)[0]
+    xo, ito, relo, st = O.cg(b, rtol=1e-12)
+    assert I["status"] == 0 and I["rel_res"] <= 1e-12
+    # true residual through the oracle operator
+    assert np.linalg.norm(b - O.kn(x)) <= 2e-12 * np.linalg.norm(b)
+    if name == "c1":
+        # cubic cells: the Jacobi diagonal is one scalar, PCG from zero stays in
+        # range(K_n) and returns the same minimum-norm solution as plain CG
+        assert abs(int(I["iters"]) - ito) <= max(2, ito // 20)
+        assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+    else:
+        # non-cubic cells: Jacobi differs per edge direction, so PCG picks
+        # another pseudo-inverse solution (a gradient field apart): compare the
+        # gauge-invariant flux C x and K_n x
+        assert np.linalg.norm(O.curl(x) - O.curl(xo)) <= 1e-10 * np.linalg.norm(O.curl(xo))
+        assert np.linalg.norm(O.kn(x) - O.kn(xo)) <= 1e-11 * np.linalg.norm(b)
+
+
+def test_solve_prev_start_and_zero_rhs(ec, oracle_mod):
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    b = O.source(3, 1e-3)
+    xo, *_ = O.cg(b, rtol=1e-13)
+    x0 = 0.9 * xo
+    info = G.info(1)
+    x = G.solve(G.tensor(b), x=G.tensor(x0), method=ec.SV_PREV, rtol=1e-12, info=info)
+    I = ec.info_array(info)[0]
+    assert I["status"] == 0
+    assert I["r0_rel"] == pytest.approx(np.linalg.norm(b - O.kn(x0)) / np.linalg.norm(b), rel=1e-8)
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+    # b = 0: x = 0 after 0 iterations, for any start
+    z = G.zeros()
+    x = G.solve(z, x=G.tensor(x0), method=ec.SV_PREV, rtol=1e-12, info=info)
+    I = ec.info_array(info)[0]
+    assert I["iters"] == 0 and I["status"] == 0 and not x.cpu().numpy().any()
+    x = G.solve(z, method=ec.SV_ZERO, info=info)
+    assert ec.info_array(info)[0]["iters"] == 0 and not x.cpu().numpy().any()
+
+
+def test_solve_maxit_reports_not_converged(ec, oracle_mod):
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    b = O.source(3, 1e-3)
+    info = G.info(1)
+    G.solve(G.tensor(b), method=ec.SV_ZERO, rtol=1e-14, maxit=3, info=info)
+    I = ec.info_array(info)[0]
+    assert I["status"] == -3 and I["iters"] == 3
+    # and the same three iterations as the oracle's CG
+    xo, it, _, st = O.cg(b, rtol=1e-14, maxit=3)
+    assert st == -3
+
+
+# ------------------------------------------------------- start vectors
+def time_window(O, dt, steps):
+    """Consecutive CPL solutions of the oracle's own time loop."""
+    A = np.zeros(O.n_pad)
+    sc = np.zeros(O.n_pad)
+    out = []
+    for m in range(steps):
+        A, sc, *_ = O.run(dt, 1, rtol=1e-13, A=A, sc=sc, m0=m)
+        out.append(sc.copy())
+    return out, A
+
+
+def test_spe_start_parity_and_sliding_window(ec, oracle_mod):
+    from oracle.startvec import spe_start
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    dt = 0.9 * 2 / O.power(iters=40)
+    sols, A = time_window(O, dt, 9)
+    b = O.kcnT(synth.random_vector(O.n_pad, O.C, 9))
+    seq = ec.SEQ_USER
+    G.history_reset(seq)
+    for k, v in enumerate(sols):
+        G.history_push(seq, ec.SV_SPE, 5, G.tensor(v))
+        if k in (0, 2, 4, 8):
+            x0 = G.start_vector(seq, ec.SV_SPE, 5, G.tensor(b)).cpu().numpy()
+            ref = spe_start(O, sols[max(0, k - 4):k + 1], b)
+            assert np.linalg.norm(x0 - ref) <= 1e-9 * np.linalg.norm(ref), k
+    # Galerkin orthogonality of the GPU start vector on the window
+    r = b - O.kn(x0)
+    for v in sols[-5:]:
+        assert abs(v @ r) <= 1e-9 * np.linalg.norm(v) * np.linalg.norm(b)
+
+
+def test_spe_exact_and_random_window(ec, oracle_mod):
+    from oracle.startvec import spe_start
+    G, O, _ = pair(ec, oracle_mod, "small")
+    win = [O.kn(synth.random_vector(O.n_pad, O.N, 30 + s)) for s in range(6)]
+    seq = ec.SEQ_ADJ
+    G.history_reset(seq)
+    for v in win:
+        G.history_push(seq, ec.SV_SPE, 6, G.tensor(v))
+    x = win[1] - 0.5 * win[4]
+    x0 = G.start_vector(seq, ec.SV_SPE, 6, G.tensor(O.kn(x))).cpu().numpy()
+    assert np.linalg.norm(x0 - x) <= 1e-10 * np.linalg.norm(x)
+    b = O.source(1, 1e-3) + O.kcnT(synth.random_vector(O.n_pad, O.C, 4))
+    x0 = G.start_vector(seq, ec.SV_SPE, 6, G.tensor(b)).cpu().numpy()
+    ref = spe_start(O, win, b)
+    assert np.linalg.norm(x0 - ref) <= 1e-10 * np.linalg.norm(ref)
+    # a dependent push does not grow the basis
+    G.history_push(seq, ec.SV_SPE, 6, G.tensor(2.0 * win[5] - win[0]))
+    x1 = G.start_vector(seq, ec.SV_SPE, 6, G.tensor(b)).cpu().numpy()
+    assert np.linalg.norm(x1 - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("eps,kmax,window", [(0.0, 6, "random"), (1e-4, 3, "time"),
+                                             (1e-4, 6, "time")])
+def test_pod_start_parity(ec, oracle_mod, eps, kmax, window):
+    """Gram-eigen POD (GPU) vs SVD POD (oracle).  Without truncation the test
+    uses a well-conditioned window: the method of snapshots squares the
+    condition number, so modes below ~1e-8 sigma_1 are not resolved; the
+    paper's eps_POD = 1e-4 keeps only resolved modes."""
+    from oracle.startvec import pod_start
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    if window == "time":
+        dt = 0.9 * 2 / O.power(iters=40)
+        sols, _ = time_window(O, dt, 8)
+    else:
+        sols = [O.kn(synth.random_vector(O.n_pad, O.N, 50 + s)) for s in range(8)]
+    win = sols[-6:]
+    seq = ec.SEQ_USER
+    G.history_reset(seq)
+    for v in sols:
+        G.history_push(seq, ec.SV_POD, 6, G.tensor(v))
+    b = O.kcnT(synth.random_vector(O.n_pad, O.C, 12))
+    info = G.info(1)
+    x0 = G.start_vector(seq, ec.SV_POD, 6, G.tensor(b), pod_kmax=kmax, pod_eps=eps,
+                        info=info).cpu().numpy()
+    ref, k, inf = pod_start(O, win, b, eps=eps, kmax=kmax)
+    I = ec.info_array(info)[0]
+    assert I["basis_cols"] == k
+    assert I["pod_info"] == pytest.approx(inf, rel=1e-8)
+    assert np.linalg.norm(x0 - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+# ----------------------------------------------------------- trajectories
+@pytest.mark.parametrize("method,window", [(0, 5), (1, 5), (2, 5), (3, 5)])
+def test_trajectory_c1(ec, oracle_mod, method, window):
+    """200 explicit Euler steps of the linear case, every start vector, at
+    rtol 1e-12 on both sides: relative error of A <= 1e-10 (sampled every 40)."""
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    dt = 0.9 * 2 / O.power(iters=60)
+    opts = ec.step_opts(method, window=window, pod_kmax=window, pod_eps=1e-4, rtol=1e-12)
+    A = G.zeros()
+    Ao = np.zeros(O.n_pad)
+    sc = np.zeros(O.n_pad)
+    for blk in range(5):
+        G.run(A, 40 * blk, 40, dt, opts)
+        Ao, sc, *_ = O.run(dt, 40, rtol=1e-12, A=Ao, sc=sc, m0=40 * blk)
+        got = A.cpu().numpy()
+        assert np.linalg.norm(got - Ao) <= 1e-10 * np.linalg.norm(Ao), blk
+        assert np.linalg.norm(O.curl(got) - O.curl(Ao)) <= 1e-10 * np.linalg.norm(O.curl(Ao))
+    assert G.counters()["worst_status"] == 0
+
+
+def test_trajectory_nonlinear16(ec, oracle_mod):
+    """Saturating Brauer iron (peak |B| > 1 T) at N = 16.
+
+    Zero-start PCG with a scalar Jacobi diagonal returns the minimum-norm
+    pseudo-inverse solution, so that trajectory must match the oracle's edge
+    by edge.  SPE start vectors carry a gradient (null-space) part into a_n
+    that PCG never removes; everything that part cannot reach (a_c, the face
+    fluxes b = C a, and K_n a_n) must still match."""
+    G, O, wl = pair(ec, oracle_mod, "nl16")
+    dt = 0.5 * 2 / O.power(iters=60)
+    Ao, *_ = O.run(dt, 60, rtol=1e-12)
+    B = O.cell_B(Ao)[wl.cell_mat.astype(bool)]
+    assert np.sqrt((B ** 2).sum(1)).max() > 1.0
+    nrm = np.linalg.norm
+    for method in (ec.SV_ZERO, ec.SV_SPE):
+        G.counters_reset()
+        A = G.zeros()
+        G.run(A, 0, 60, dt, ec.step_opts(method, window=8, rtol=1e-12))
+        got = A.cpu().numpy()
+        assert G.counters()["worst_status"] == 0
+        if method == ec.SV_ZERO:
+            assert nrm(got - Ao) <= 1e-10 * nrm(Ao)
+            continue
+        c = O.C
+        assert nrm((got - Ao)[c]) <= 1e-10 * nrm(Ao[c])
+        assert nrm(O.curl(got) - O.curl(Ao)) <= 1e-10 * nrm(O.curl(Ao))
+        an, ano = np.where(O.N, got, 0.0), np.where(O.N, Ao, 0.0)
+        assert nrm(O.kn(an) - O.kn(ano)) <= 1e-9 * nrm(O.kn(ano))
+        assert nrm(got - Ao) <= 1e-4 * nrm(Ao)        # gauge part stays small
+
+
+def test_step_info_records(ec, oracle_mod):
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    dt = 0.9 * 2 / O.power(iters=40)
+    info = G.info(2 * 10)
+    A = G.zeros()
+    G.run(A, 0, 10, dt, ec.step_opts(ec.SV_SPE, window=5, rtol=1e-10), info=info)
+    I = ec.info_array(info)
+    assert (I["status"] == 0).all()
+    assert (I["rel_res"] <= 1e-10).all()
+    src, cpl = I[0::2], I[1::2]
+    assert (src["iters"][2:] == 0).all()         # j^m is parallel to the stored solution
+    assert (src["basis_cols"][1:] == 1).all()
+    c = G.counters()
+    assert c["steps"] == 10 and c["iters_src"] == src["iters"].sum()
+    assert c["iters_cpl"] == cpl["iters"].sum()
+
+
+def test_set_state_and_continue(ec, oracle_mod):
+    """ec_set_state from an oracle state, then steps: same as continuing the oracle."""
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    dt = 0.9 * 2 / O.power(iters=40)
+    Ao, sc, *_ = O.run(dt, 15, rtol=1e-13)
+    A = G.tensor(Ao)
+    G.set_state(A, rtol=1e-13)
+    G.run(A, 15, 10, dt, ec.step_opts(ec.SV_PREV, rtol=1e-12))
+    A2, *_ = O.run(dt, 10, rtol=1e-12, A=Ao, sc=sc, m0=15)
+    assert np.linalg.norm(A.cpu().numpy() - A2) <= 1e-10 * np.linalg.norm(A2)
+
+
+def test_cfl_power_method(ec, oracle_mod):
+    """Eq. (8) bound: C1's top generalized eigenvalues are clustered (ratio
+    0.995), so both power methods are checked against the dense eigenvalue:
+    a Rayleigh quotient never exceeds lambda_max and gets within 1e-3."""
+    from oracle.dense import Dense
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    lam_d = Dense(O).gen_eig()[0].max()
+    lam = G.cfl(iters=400, rtol=1e-12)
+    assert lam <= lam_d * (1 + 1e-9) and lam >= lam_d * (1 - 1e-3)
+    G, O, _ = pair(ec, oracle_mod, "nl16")
+    assert G.cfl(iters=300, rtol=1e-12) == pytest.approx(O.power(iters=300, rtol=1e-12), rel=1e-3)
+
+
+def test_bad_pointer_rejected(ec, oracle_mod):
+    import torch
+    G, O, _ = pair(ec, oracle_mod, "c1")
+    x = torch.zeros(G.n_pad + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ec.ECError) as e:
+        G.apply(ec.OP_KN, x[1:], out=G.zeros())
+    assert e.value.code == -1
+    with pytest.raises(ec.ECError):
+        G.solve(G.zeros(), method=ec.SV_SPE, window=G.window_cap + 1)
