@@ -154,6 +154,19 @@ int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64_t bytes,
  *                 reluctivity evaluated at x (eq. 3, first block row). */
 int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y);
 
+/* Grad-div weight of the SPE projection (eq. 10; Sec. II names grad-div
+ * regularisation as the alternative to the weak gauging of PCG).  The SPE
+ * start vector solves the projected system with Q^T (K_n + eta D^T D) Q,
+ * D = discrete divergence G^T at the free nodes (interior nodes that no
+ * conducting edge ends on), eta = factor * (half the mean K_n diagonal of an
+ * edge off the conductor).  K_n^+ b has zero divergence there, so the exact
+ * solution is unchanged; the term stops the projection from amplifying the
+ * gradient (null-space) part that PCG never removes from a start vector.
+ * factor = 0 gives the projection as printed; the default is 1.  A change
+ * empties the SPE histories.  EC_ERR_ARG for a negative or non-finite factor.
+ * POD (eqs. 11-14) is unaffected: its truncation drops those directions. */
+int32_t ec_set_gauge_penalty(ec_handle h, double factor);
+
 /* Sequence histories (eq. 9: one history per right-hand-side sequence).
  * reset empties it; push appends a solution x (device padded array). */
 int32_t ec_history_reset(ec_handle h, int32_t seq);

@@ -9,12 +9,52 @@
   singular values by the threshold eps_POD = 1e-4 (keep sigma_i >= eps sigma_1,
   at most kmax modes), the relative information criterion of eq. (13), and
   the same Galerkin projection on the first k left singular vectors.
+* Gauge penalty (reading of Sec. II, where grad-div regularisation is named as
+  an alternative to the weak gauging of Krylov solvers): the projected matrix
+  is U^T (K_n + eta D^T D) U, D the discrete divergence at the free nodes.
+  K_n^+ b has zero divergence there, so the exact solution is unchanged; the
+  penalty only stops the projection from amplifying the gradient (null-space)
+  part that earlier solutions carry, which PCG never removes.  penalty = 0 is
+  the projection of eq. (10) as printed.  POD keeps penalty = 0: its
+  truncation (eq. 12) already drops the weak directions that carry that part.
 
 K_n products come from the oracle's operator.  Everything else is numpy.
 """
 from __future__ import annotations
 
 import numpy as np
+
+from .dense import divergence
+
+
+def free_nodes(P):
+    """Interior grid nodes that are not an end of any conducting edge."""
+    nx, ny, nz = P.wl.n
+    S = (nx + 1) * (ny + 1) * (nz + 1)
+    k, r = np.divmod(np.arange(S), (nx + 1) * (ny + 1))
+    j, i = np.divmod(r, nx + 1)
+    free = (i > 0) & (i < nx) & (j > 0) & (j < ny) & (k > 0) & (k < nz)
+    step = (1, nx + 1, (nx + 1) * (ny + 1))
+    for c in range(3):
+        tail = np.flatnonzero(P.C[c * S:(c + 1) * S])
+        free[tail] = False
+        free[tail + step[c]] = False
+    return free
+
+
+def gauge_rows(P, x, free=None):
+    """D x: the divergence G^T x at the free nodes."""
+    free = free_nodes(P) if free is None else free
+    return divergence(P.wl.n, np.asarray(x, np.float64))[free]
+
+
+def gauge_eta(P):
+    """Penalty weight: half the mean K_n diagonal of a free edge, so that
+    eta D^T D has the diagonal of K_n (2 nodes per edge)."""
+    h = [L / n for L, n in zip(P.wl.length, P.wl.n)]
+    d = [2.0 * P.wl.nu0 * (h[(c + 1) % 3] / (h[c] * h[(c + 2) % 3]) +
+                           h[(c + 2) % 3] / (h[c] * h[(c + 1) % 3])) for c in range(3)]
+    return 0.5 * sum(d) / 3.0
 
 
 def mgs_basis(X, dep_tol=1e-10):
@@ -36,20 +76,25 @@ def mgs_basis(X, dep_tol=1e-10):
     return U
 
 
-def galerkin(P, U, b):
-    """x0 = U (U^T K_n U)^{-1} U^T b for a list of basis vectors U."""
+def galerkin(P, U, b, penalty=1.0):
+    """x0 = U (U^T (K_n + eta D^T D) U)^{-1} U^T b for a list of basis vectors U,
+    eta = penalty * gauge_eta(P)."""
     if len(U) == 0:
         return np.zeros_like(b)
     Um = np.column_stack(U)
     KU = np.column_stack([P.kn(u) for u in U])
     H = Um.T @ KU
+    if penalty:
+        free = free_nodes(P)
+        DU = np.column_stack([gauge_rows(P, u, free) for u in U])
+        H = H + penalty * gauge_eta(P) * (DU.T @ DU)
     y = np.linalg.solve(H, Um.T @ b)
     return Um @ y
 
 
-def spe_start(P, X, b, dep_tol=1e-10):
+def spe_start(P, X, b, dep_tol=1e-10, penalty=1.0):
     """SPE start vector (eq. 10) over the window X of previous solutions."""
-    return galerkin(P, mgs_basis(X, dep_tol), b)
+    return galerkin(P, mgs_basis(X, dep_tol), b, penalty)
 
 
 def pod_basis(X, eps=1e-4, kmax=None):
@@ -65,7 +110,7 @@ def pod_basis(X, eps=1e-4, kmax=None):
     return [Us[:, i] for i in range(k)], k, info, s
 
 
-def pod_start(P, X, b, eps=1e-4, kmax=None):
+def pod_start(P, X, b, eps=1e-4, kmax=None, penalty=0.0):
     """POD start vector (eq. 14); returns (x0, k, information of eq. 13)."""
     U, k, info, _ = pod_basis(X, eps, kmax)
-    return galerkin(P, U, b), k, info
+    return galerkin(P, U, b, penalty), k, info

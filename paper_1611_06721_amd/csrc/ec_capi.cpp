@@ -56,6 +56,9 @@ struct ec_problem {
     double *xs_d = nullptr, *sj = nullptr, *sc = nullptr, *ac = nullptr, *bcpl = nullptr;
     double *rb[2] = {}, *wb[2] = {}, *sb[2] = {}, *pv = nullptr;
     double *w = nullptr, *t2 = nullptr, *t3 = nullptr, *t4 = nullptr;
+    // grad-div weight of the SPE projection: eta0 = half the mean diagonal of
+    // K_n on edges off the conductor, scaled by the caller's factor
+    double eta0 = 0.0, gauge_rel = 1.0;
     // FP32 vectors of the refinement's inner solve
     float *frb[2] = {}, *fwb[2] = {}, *fsb[2] = {}, *fpv = nullptr, *fd = nullptr;
     double *hist[EC_NSEQ] = {};
@@ -164,6 +167,7 @@ static int32_t assemble(ec_problem *h, const ec_grid *grid, const ec_materials *
     g.dinv[0] = 1.0 / (2.0 * (g.wy + g.wz));
     g.dinv[1] = 1.0 / (2.0 * (g.wz + g.wx));
     g.dinv[2] = 1.0 / (2.0 * (g.wx + g.wy));
+    h->eta0 = (1.0 / g.dinv[0] + 1.0 / g.dinv[1] + 1.0 / g.dinv[2]) / 6.0;
 
     h->cmat.assign(mat->cell_mat, mat->cell_mat + h->ncell);
     int lo[3] = {nx, ny, nz}, hi[3] = {-1, -1, -1};
@@ -547,10 +551,18 @@ static void seq_push(ec_problem *h, int seq, int method, const double *x)
     lincomb(l, st);
     dense(h, seq, OP_SPE_PUSH3);
     spmv_slot(h->g, h->t2, h->t3, KQ, Q, &sd->slot_new, h->ld, &sd->active, st);
+    // new column of Q^T (K_n + eta D^T D) Q: the grad-div term keeps the
+    // projection from amplifying the gradient part of the window
+    const double eta = h->gauge_rel * h->eta0;
+    const double *kq = h->t3;
+    if (eta > 0.0) {
+        graddiv(h->g, h->t2, h->t3, h->t4, eta, &sd->active, st);
+        kq = h->t4;
+    }
     MdArgs m2 = md_args(h);
-    m2.A = KQ;
+    m2.A = Q;
     m2.kp = &sd->ncol_md;
-    m2.B[0] = {h->t2, nullptr};
+    m2.B[0] = {kq, nullptr};
     m2.nb = 1;
     m2.active = &sd->active;
     multidot(m2, st);
@@ -740,6 +752,20 @@ extern "C" int32_t ec_solve(ec_handle h, int32_t seq, int32_t method, int32_t wi
     const double eps = (h->seq_method[seq] == method && h->seq_win[seq] == window)
                            ? h->seq_eps[seq] : 1e-4;
     return do_solve(h, seq, method, window, kmax, eps, b, nullptr, x, opts, dev_info, true);
+}
+
+extern "C" int32_t ec_set_gauge_penalty(ec_handle h, double factor)
+{
+    NEED_BOUND(h);
+    if (!(factor >= 0.0) || !std::isfinite(factor))
+        return fail(h, EC_ERR_ARG, "factor must be finite and >= 0");
+    if (factor != h->gauge_rel) {
+        // stored projected matrices hold the old weight: start SPE histories anew
+        for (int s = 0; s < EC_NSEQ; ++s)
+            if (h->seq_method[s] == EC_SV_SPE) seq_reset(h->seq_d + s, h->st);
+        h->gauge_rel = factor;
+    }
+    return launch_check(h, "gauge penalty");
 }
 
 extern "C" int32_t ec_history_reset(ec_handle h, int32_t seq)

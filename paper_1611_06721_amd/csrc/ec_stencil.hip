@@ -93,6 +93,54 @@ void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st)
     spmv_launch_box<float>(g, x, y, lo, ext, st, nullptr, nullptr, nullptr, 0, nullptr);
 }
 
+// ------------------------------------------------------- grad-div penalty
+// G^T x at node (i,j,k) when the node is free (interior, and no conducting
+// edge ends there), else 0.  G phi puts phi(head) - phi(tail) on an edge.
+__device__ __forceinline__ double free_div(const Geo &g, const double *__restrict__ x, int i,
+                                           int j, int k)
+{
+    if (i <= 0 || i >= g.nx || j <= 0 || j >= g.ny || k <= 0 || k >= g.nz) return 0.0;
+    const int64_t oj = g.px, ok = (int64_t)g.px * g.py;
+    const int64_t n = k * ok + j * oj + i;
+    if (edge_cls(g, 0, i, j, k, n) == 1 || edge_cls(g, 0, i - 1, j, k, n - 1) == 1 ||
+        edge_cls(g, 1, i, j, k, n) == 1 || edge_cls(g, 1, i, j - 1, k, n - oj) == 1 ||
+        edge_cls(g, 2, i, j, k, n) == 1 || edge_cls(g, 2, i, j, k - 1, n - ok) == 1)
+        return 0.0;
+    const int64_t S = g.S;
+    return (x[n - 1] - x[n]) + (x[S + n - oj] - x[S + n]) + (x[2 * S + n - ok] - x[2 * S + n]);
+}
+
+// y = kx + eta D^T D x on nonconducting edges (kx elsewhere), D the divergence
+// at the free nodes: the grad-div term that makes the SPE projection see the
+// gradient (null-space) part of its basis.  One thread per node.
+__global__ void __launch_bounds__(256)
+    k_graddiv(Geo g, const double *__restrict__ x, const double *__restrict__ kx,
+              double *__restrict__ y, double eta, const int *active)
+{
+    if (active && !*active) return;
+    const int64_t n = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    if (n >= g.S) return;
+    int i, j, k;
+    decode(g, n, i, j, k);
+    const double d0 = free_div(g, x, i, j, k);
+    const double dh[3] = {free_div(g, x, i + 1, j, k), free_div(g, x, i, j + 1, k),
+                          free_div(g, x, i, j, k + 1)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t ix = (int64_t)c * g.S + n;
+        double v = kx[ix];
+        if (edge_cls(g, c, i, j, k, n) == 2) v += eta * (dh[c] - d0);
+        y[ix] = v;
+    }
+}
+
+void graddiv(const Geo &g, const double *x, const double *kx, double *y, double eta,
+             const int *active, hipStream_t st)
+{
+    const int blocks = (int)((g.S + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_graddiv, dim3(blocks), dim3(kTile), 0, st, g, x, kx, y, eta, active);
+}
+
 // ------------------------------------------------------------------- CG
 __device__ __forceinline__ double dsel(const double (&d)[3], int c)
 {

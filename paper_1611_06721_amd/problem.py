@@ -123,6 +123,10 @@ class Problem:
                                         C.byref(o), _ptr(info)))
         return x
 
+    def set_gauge_penalty(self, factor):
+        with self._on_stream():
+            self._chk(self.lib.ec_set_gauge_penalty(self.h, factor))
+
     def history_reset(self, seq):
         with self._on_stream():
             self._chk(self.lib.ec_history_reset(self.h, seq))

@@ -207,6 +207,41 @@ def test_spe_exact_and_random_window(ec, oracle_mod):
     assert np.linalg.norm(x1 - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+def test_spe_gauge_penalty(ec, oracle_mod):
+    """A window holding a pure gradient (a null vector of K_n): with the
+    grad-div term the start vector is x* itself, as in the oracle; with the
+    term switched off a normal window still matches the printed projection."""
+    from oracle.dense import gradient
+    from oracle.startvec import free_nodes, spe_start
+    G, O, wl = pair(ec, oracle_mod, "c1")
+    dt = 0.9 * 2 / O.power(iters=40)
+    sols, _ = time_window(O, dt, 6)
+    nx, ny, nz = wl.n
+    S = (nx + 1) * (ny + 1) * (nz + 1)
+    phi = np.where(free_nodes(O), np.random.default_rng(3).standard_normal(S), 0.0)
+    g = gradient(wl.n, phi)
+    xs = sols[-1]
+    seq = ec.SEQ_USER
+    G.history_reset(seq)
+    for v in (sols[-3], g, xs):
+        G.history_push(seq, ec.SV_SPE, 5, G.tensor(v))
+    b = O.kn(xs)
+    x0 = G.start_vector(seq, ec.SV_SPE, 5, G.tensor(b)).cpu().numpy()
+    assert np.linalg.norm(x0 - xs) <= 1e-9 * np.linalg.norm(xs)
+    b2 = O.kcnT(synth.random_vector(O.n_pad, O.C, 14))
+    x1 = G.start_vector(seq, ec.SV_SPE, 5, G.tensor(b2)).cpu().numpy()
+    ref = spe_start(O, [sols[-3], g, xs], b2)
+    assert np.linalg.norm(x1 - ref) <= 1e-9 * np.linalg.norm(ref)
+    G.set_gauge_penalty(0.0)
+    for v in sols[-5:]:
+        G.history_push(seq, ec.SV_SPE, 5, G.tensor(v))
+    x2 = G.start_vector(seq, ec.SV_SPE, 5, G.tensor(b2)).cpu().numpy()
+    ref0 = spe_start(O, sols[-5:], b2, penalty=0.0)
+    assert np.linalg.norm(x2 - ref0) <= 1e-9 * np.linalg.norm(ref0)
+    with pytest.raises(ec.ECError):
+        G.set_gauge_penalty(-1.0)
+
+
 @pytest.mark.parametrize("eps,kmax,window", [(0.0, 6, "random"), (1e-4, 3, "time"),
                                              (1e-4, 6, "time")])
 def test_pod_start_parity(ec, oracle_mod, eps, kmax, window):
@@ -272,8 +307,9 @@ def test_trajectory_nonlinear16(ec, oracle_mod):
     assert np.sqrt((B ** 2).sum(1)).max() > 1.0
     nrm = np.linalg.norm
     for method in (ec.SV_ZERO, ec.SV_SPE):
-        G.counters_reset()
         A = G.zeros()
+        G.set_state(A, rtol=1e-12)           # s_c = 0 and empty histories again
+        G.counters_reset()
         G.run(A, 0, 60, dt, ec.step_opts(method, window=8, rtol=1e-12))
         got = A.cpu().numpy()
         assert G.counters()["worst_status"] == 0
@@ -285,7 +321,9 @@ def test_trajectory_nonlinear16(ec, oracle_mod):
         assert nrm(O.curl(got) - O.curl(Ao)) <= 1e-10 * nrm(O.curl(Ao))
         an, ano = np.where(O.N, got, 0.0), np.where(O.N, Ao, 0.0)
         assert nrm(O.kn(an) - O.kn(ano)) <= 1e-9 * nrm(O.kn(ano))
-        assert nrm(got - Ao) <= 1e-4 * nrm(Ao)        # gauge part stays small
+        # the grad-div term of the projection keeps the gradient part at the
+        # level of the solver tolerance (it grows without bound otherwise)
+        assert nrm(got - Ao) <= 1e-6 * nrm(Ao)
 
 
 def test_step_info_records(ec, oracle_mod):

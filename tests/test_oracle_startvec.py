@@ -118,3 +118,71 @@ def test_spe_start_reduces_iterations(setup):
     _, it_spe, _, _ = P.cg(b_next, x0=x_spe, rtol=1e-8)
     _, it_zero, _, _ = P.cg(b_next, rtol=1e-8)
     assert it_spe < it_zero
+
+
+def test_gauge_rows_closed_form_and_range_space(setup):
+    """D G delta_v is the 7-point graph Laplacian (6 at a free node v, -1 at
+    its free neighbours); D vanishes on range(K_n) and on the minimum-norm
+    solutions, which are orthogonal to every gradient."""
+    from oracle.dense import gradient
+    from oracle.startvec import free_nodes, gauge_rows
+    P, dt, sols = setup
+    nx, ny, nz = P.wl.n
+    S = (nx + 1) * (ny + 1) * (nz + 1)
+    free = free_nodes(P)
+    node = lambda i, j, k: (k * (ny + 1) + j) * (nx + 1) + i
+    v = node(2, 3, 2)
+    assert free[v] and not free[node(0, 3, 2)]
+    phi = np.zeros(S)
+    phi[v] = 1.0
+    g = gradient(P.wl.n, phi)
+    assert not g[~P.N].any() and np.abs(P.kn(g)).max() < 1e-9 * np.abs(P.kn(sols[-1])).max()
+    full = np.zeros(S)
+    full[free] = gauge_rows(P, g, free)
+    assert full[v] == 6.0
+    for w in (node(1, 3, 2), node(3, 3, 2), node(2, 2, 2), node(2, 4, 2), node(2, 3, 1),
+              node(2, 3, 3)):
+        assert full[w] == (-1.0 if free[w] else 0.0)
+    assert np.abs(full).sum() == 6.0 + free[[node(1, 3, 2), node(3, 3, 2), node(2, 2, 2),
+                                              node(2, 4, 2), node(2, 3, 1), node(2, 3, 3)]].sum()
+    for x in sols[-3:] + [P.kn(synth.random_vector(P.n_pad, P.N, 5))]:
+        # each entry is a sum of six edge values of size up to max|x|
+        assert np.abs(gauge_rows(P, x, free)).max() <= 1e-10 * np.abs(x).max()
+
+
+def test_gauge_eta_is_half_the_kn_diagonal(setup):
+    from oracle.startvec import gauge_eta
+    P, dt, sols = setup
+    nx, ny, nz = P.wl.n
+    S = (nx + 1) * (ny + 1) * (nz + 1)
+    for c in range(3):
+        e = np.zeros(P.n_pad)
+        slot = c * S + (2 * (ny + 1) + 2) * (nx + 1) + 1     # an edge far from the iron
+        assert P.N[slot]
+        e[slot] = 1.0
+        assert gauge_eta(P) == pytest.approx(0.5 * P.kn(e)[slot], rel=1e-14)
+
+
+def test_gauge_penalty_removes_null_directions(setup):
+    """Window = {x*, gradient}: the projection of eq. (10) is singular (the
+    gradient has no K_n energy); with the penalty it returns x* itself.  On a
+    window inside range(K_n) the penalty changes nothing."""
+    from oracle.dense import gradient
+    from oracle.startvec import free_nodes, mgs_basis, spe_start
+    P, dt, sols = setup
+    nx, ny, nz = P.wl.n
+    S = (nx + 1) * (ny + 1) * (nz + 1)
+    rng = np.random.default_rng(3)
+    phi = np.where(free_nodes(P), rng.standard_normal(S), 0.0)
+    g = gradient(P.wl.n, phi)
+    xs = sols[-1]
+    b = P.kn(xs)
+    U = np.column_stack(mgs_basis([xs, g]))
+    H = U.T @ np.column_stack([P.kn(u) for u in U.T])
+    assert np.linalg.cond(H) > 1e10
+    x0 = spe_start(P, [xs, g], b)
+    assert np.linalg.norm(x0 - xs) <= 1e-10 * np.linalg.norm(xs)
+    X = sols[-6:-1]
+    bb = P.kcnT(synth.random_vector(P.n_pad, P.C, 8))
+    a, z = spe_start(P, X, bb, penalty=1.0), spe_start(P, X, bb, penalty=0.0)
+    assert np.linalg.norm(a - z) <= 1e-8 * np.linalg.norm(z)
