@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+COPY_BYTES = 512 << 20
 METRIC = "Euler steps/sec at rel. residual 1e-8; PCG iters/step; SpMV HBM GB/s"
 
 
@@ -45,32 +46,36 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def method_opts(ec, name, budget, rtol):
+def method_opts(ec, name, rtol, graph_iters=(0, 0)):
+    kw = dict(rtol=rtol, maxit=100000, graph_iters=graph_iters)
     if name == "spe":
-        return ec.step_opts(ec.SV_SPE, window=8, pod_kmax=8, rtol=rtol, maxit=budget)
+        return ec.step_opts(ec.SV_SPE, window=8, pod_kmax=8, **kw)
     if name == "pod":
-        return ec.step_opts(ec.SV_POD, window=20, pod_kmax=10, pod_eps=1e-4, rtol=rtol,
-                            maxit=budget)
+        return ec.step_opts(ec.SV_POD, window=20, pod_kmax=10, pod_eps=1e-4, **kw)
     if name == "prev":
-        return ec.step_opts(ec.SV_PREV, window=1, rtol=rtol, maxit=budget)
-    return ec.step_opts(ec.SV_ZERO, window=1, rtol=rtol, maxit=budget)
+        return ec.step_opts(ec.SV_PREV, window=1, **kw)
+    return ec.step_opts(ec.SV_ZERO, window=1, **kw)
 
 
 def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
-    """Eager warm-up (sizes the per-solve iteration budget of the graph), then
-    `steps` graph replays from rest, timed with events on the bound stream."""
-    A = G.zeros()
-    G.set_state(A, rtol=rtol)
-    info = G.info(2 * warmup)
-    G.run(A, 0, warmup, dt, method_opts(ec, name, 100000, rtol), info=info)
-    its = ec.info_array(info)["iters"]
-    budget = int(max(its.max() * 1.5, its.max() + 16))
-    for attempt in range(3):
-        A.zero_()
+    """`warmup` eager steps from rest (not timed; they also fill the start-vector
+    histories), then `steps` replays of the captured step, continuing the same
+    run, timed with events on the library's stream.  Each captured solve issues
+    a fixed number of PCG iteration kernels, sized from the second half of the
+    warm-up; if any replayed solve needs more, it reports NOT_CONVERGED and the
+    whole measurement is repeated with twice the budget."""
+    budgets = None
+    for attempt in range(4):
+        A = G.zeros()
         G.set_state(A, rtol=rtol)
-        G.set_step(0)
+        info = G.info(2 * warmup)
+        G.run(A, 0, warmup, dt, method_opts(ec, name, rtol), info=info)
+        its = ec.info_array(info)["iters"]
+        if budgets is None:
+            h = warmup // 2
+            budgets = [int(1.5 * its[2 * h + q::2].max()) + 4 for q in (0, 1)]
         G.counters_reset()
-        graph = G.graph_capture(A, dt, method_opts(ec, name, budget, rtol))
+        graph = G.graph_capture(A, dt, method_opts(ec, name, rtol, tuple(budgets)))
         torch.cuda.synchronize()
         s = G.stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -84,8 +89,8 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
         del graph
         if c["worst_status"] == 0 and c["steps"] == steps:
             break
-        log(f"[bench] {name}: budget {budget} insufficient (status {c['worst_status']}), retry")
-        budget *= 2
+        log(f"[bench] {name}: budget {budgets} insufficient (status {c['worst_status']}), retry")
+        budgets = [2 * b for b in budgets]
     else:
         raise RuntimeError(f"{name}: solves did not converge within the graph budget")
     return {
@@ -94,7 +99,7 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
         "iters_per_step": (c["iters_src"] + c["iters_cpl"]) / steps,
         "iters_src_per_step": c["iters_src"] / steps,
         "iters_cpl_per_step": c["iters_cpl"] / steps,
-        "graph_iteration_budget": budget,
+        "graph_iteration_budget": list(budgets),
         "final_state_norm": float(A.norm().item()),
     }, A
 
@@ -149,7 +154,7 @@ def traffic_record(kernel, workload):
 
 def cpu_baseline(steps, dt):
     """The oracle (plain FP64 C, zero-start CG) on the host cores: the first
-    `steps` steps of the same workload."""
+    `steps` steps of the same workload (about 20 s at 300 steps)."""
     import oracle
     import synth
     threads = min(os.cpu_count() or 1, 16)
@@ -170,9 +175,12 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--methods", default="spe,pod,prev,zero")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the dominant-kernel timing and a 512 MiB device copy "
+                         "(the reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -188,6 +196,16 @@ def main():
     rtol = 1e-8
     wl = synth.nonlinear(48)
     G = ec.Problem(wl, window_cap=20)
+    if args.roofline_only:
+        cg_us = time_cg_iteration(ec, torch, G)
+        x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=G.device)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel": "k_cg_iter<double>", "avg_us": round(cg_us, 3),
+                          "copy_bytes_each_way": COPY_BYTES}), flush=True)
+        return
     lam = G.cfl(iters=60, rtol=1e-10)
     dt = 0.5 * 2.0 / lam
     log(f"[bench] 48^3 nonlinear: n_pad {G.n_pad}, lambda_max {lam:.6g}, dt {dt:.4g}")

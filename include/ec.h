@@ -123,6 +123,11 @@ typedef struct {
     int32_t pod_kmax;
     double pod_eps;
     ec_solve_opts solve;
+    /* PCG iteration kernels a captured graph issues per solve, for the
+     * source and the coupling sequence; 0 = solve.maxit (at most 4096).
+     * A solve that needs more ends with EC_ERR_NOT_CONVERGED in its record
+     * and in the worst-status counter.  Eager calls ignore these. */
+    int32_t graph_iters[2];
 } ec_step_opts;
 
 /* Create a problem (host only): validates the descriptors, builds the edge

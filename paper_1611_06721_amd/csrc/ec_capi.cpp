@@ -59,6 +59,8 @@ struct ec_problem {
     // grad-div weight of the SPE projection: eta0 = half the mean diagonal of
     // K_n on edges off the conductor, scaled by the caller's factor
     double eta0 = 0.0, gauge_rel = 1.0;
+    // per-sequence iteration budget of the solves being captured (0 = maxit)
+    int graph_iters[EC_NSEQ] = {};
     // FP32 vectors of the refinement's inner solve
     float *frb[2] = {}, *fwb[2] = {}, *fsb[2] = {}, *fpv = nullptr, *fd = nullptr;
     double *hist[EC_NSEQ] = {};
@@ -591,7 +593,8 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
     hipStream_t st = h->st;
     const int maxit = a.maxit;
     if (capturing(h)) {
-        const int budget = std::min(maxit, kGraphMaxIters);
+        int budget = std::min(maxit, kGraphMaxIters);
+        if (hintable && h->graph_iters[seq] > 0) budget = std::min(budget, h->graph_iters[seq]);
         for (int i = 0; i < budget; ++i) cg_iter<T>(a, i, st);
         *n_issued = budget;
         return launch_check(h, "cg (graph)");
@@ -1025,13 +1028,18 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     int32_t rc = check_step_args(h, dt, A, opts);
     if (rc) return rc;
     if (!graph_exec) return fail(h, EC_ERR_ARG, "graph_exec is NULL");
+    if (opts->graph_iters[0] < 0 || opts->graph_iters[1] < 0)
+        return fail(h, EC_ERR_ARG, "graph_iters must be >= 0");
     // configure the histories eagerly so that no reset is recorded
     for (int s : {EC_SEQ_SRC, EC_SEQ_CPL})
         seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
     HIP_TRY(h, hipStreamSynchronize(h->st));
     hipGraph_t graph = nullptr;
     HIP_TRY(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    h->graph_iters[EC_SEQ_SRC] = opts->graph_iters[0];
+    h->graph_iters[EC_SEQ_CPL] = opts->graph_iters[1];
     rc = step_impl(h, -1, dt, A, opts, dev_info);
+    h->graph_iters[EC_SEQ_SRC] = h->graph_iters[EC_SEQ_CPL] = 0;
     hipError_t e = hipStreamEndCapture(h->st, &graph);
     if (rc) {
         if (graph) (void)hipGraphDestroy(graph);

@@ -294,6 +294,12 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
 {
     if (a.skip && *a.skip) return;
+    // a finished solve: pass the record on and leave before any reduction
+    // (graph replays issue a fixed number of these kernels)
+    if (a.ctl[it & 1].done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
+        return;
+    }
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
     const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;

@@ -28,9 +28,13 @@ def solve_opts(rtol=1e-8, maxit=100000, precision=L.PREC_FP64, inner_rtol=1e-5,
     return L.SolveOpts(rtol, maxit, precision, inner_rtol, inner_maxit, outer_max)
 
 
-def step_opts(method=L.SV_SPE, window=8, pod_kmax=None, pod_eps=1e-4, **solve):
+def step_opts(method=L.SV_SPE, window=8, pod_kmax=None, pod_eps=1e-4, graph_iters=(0, 0),
+              **solve):
+    """graph_iters: PCG iteration kernels per solve (source, coupling) in a
+    captured step; 0 = maxit."""
     kmax = window if pod_kmax is None else pod_kmax
-    return L.StepOpts(method, window, kmax, pod_eps, solve_opts(**solve))
+    return L.StepOpts(method, window, kmax, pod_eps, solve_opts(**solve),
+                      (C.c_int32 * 2)(*graph_iters))
 
 
 def info_array(info_tensor):
