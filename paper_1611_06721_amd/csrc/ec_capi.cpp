@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ec.h"
@@ -72,6 +73,8 @@ struct ec_problem {
     Ctrl *ctrl_d = nullptr;
     CgCtl *cg_d = nullptr;
     double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr;
+    unsigned *bar = nullptr;     // grid-barrier counters of the PCG tail kernel
+    int tail_blocks = 0;         // cooperative tail grid (0: no tail available)
     int seq_method[EC_NSEQ], seq_win[EC_NSEQ], seq_kmax[EC_NSEQ];
     double seq_eps[EC_NSEQ];
     int hint[EC_NSEQ];
@@ -348,6 +351,7 @@ static int64_t layout(ec_problem *h, int cap, char *base)
     h->part_cg = (double *)take(2 * 4 * (int64_t)kMaxBlocks * 8);
     h->part_md = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
     h->part_ref = (double *)take(2 * (int64_t)kMaxBlocks * 8);
+    h->bar = (unsigned *)take(9 * kBarStride * sizeof(unsigned));
     h->ld = ld;
     return off;
 }
@@ -428,6 +432,7 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
         if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->tiles = (int)((h->S + kTile - 1) / kTile);
     h->cg_blocks = choose_blocks(h);
+    h->tail_blocks = cg_tail_blocks<double>();
     h->bound = true;
     return EC_OK;
 }
@@ -594,8 +599,20 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
     const int maxit = a.maxit;
     if (capturing(h)) {
         int budget = std::min(maxit, kGraphMaxIters);
-        if (hintable && h->graph_iters[seq] > 0) budget = std::min(budget, h->graph_iters[seq]);
+        const int want = hintable ? h->graph_iters[seq] : 0;
+        const bool tail = want > 0 && want < maxit && std::is_same<T, double>::value &&
+                          h->tail_blocks > 0;
+        if (want > 0) budget = std::min(budget, want);
         for (int i = 0; i < budget; ++i) cg_iter<T>(a, i, st);
+        // rare long solves (cold start, a sudden change of the source) finish
+        // in one cooperative launch instead of failing at the budget
+        if constexpr (std::is_same<T, double>::value) {
+            if (tail) {
+                hipError_t e = cg_tail<double>(a, budget, h->tail_blocks, st);
+                if (e != hipSuccess)
+                    return fail(h, EC_ERR_HIP, "cooperative tail launch: %s", hipGetErrorString(e));
+            }
+        }
         *n_issued = budget;
         return launch_check(h, "cg (graph)");
     }
@@ -648,6 +665,7 @@ static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const
     a.skip = nullptr;
     a.tiles = h->tiles;
     a.blocks = h->cg_blocks;
+    a.bar = h->bar;
     if (mode == START_X) {
         a.mode = START_X;
         cg_init<double>(a, h->st);

@@ -137,7 +137,13 @@ struct CgArgs {
     const int *skip;         // device flag: nonzero -> kernels return at once
     int tiles;
     int blocks;
+    unsigned *bar;           // grid-barrier counters of the tail kernel (9 x kBarStride)
 };
+
+// grid barrier: counter words kBarStride apart (separate 128-byte lines);
+// bounded wait of the cooperative tail kernel
+constexpr int kBarStride = 32;
+constexpr long kSpinLimit = 1L << 22;
 
 template <typename T>
 void cg_init(const CgArgs<T> &a, hipStream_t st);
@@ -145,6 +151,12 @@ template <typename T>
 void cg_iter(const CgArgs<T> &a, int i, hipStream_t st);
 template <typename T>
 void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st);
+// blocks of the cooperative tail (one per CU, a multiple of 8; 0 on failure)
+template <typename T>
+int cg_tail_blocks();
+// iterations it0.. of an unfinished solve in one cooperative launch
+template <typename T>
+hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st);
 
 // basis products  C = [A_0..A_{p-1}, a_extra]^T [B_0..B_{nb-1}]  (FP64 MFMA)
 struct MdArgs {

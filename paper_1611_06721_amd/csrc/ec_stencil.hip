@@ -18,6 +18,8 @@
 // decision.  Stop: ||r|| <= rtol ||b|| (recursive residual).
 #include <math.h>
 
+#include <algorithm>
+
 #include "ec_device.h"
 
 namespace ec {
@@ -247,6 +249,8 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
             c0.status = EC_OK;
             c0.zero_x = zero_all;
             a.ctl[0] = c0;
+            if (a.bar)
+                for (int q = 0; q <= 8; ++q) a.bar[q * kBarStride] = 0u;
         }
     }
 }
@@ -290,36 +294,32 @@ __device__ __forceinline__ CgCtl cg_state(const CgCtl &prev, const double (&t)[4
     return c;
 }
 
+// One PCG iteration `it` by the whole grid: reduce the nprev partials of the
+// previous iteration (every block, same order), decide, then update x, p, s,
+// r, w and leave this iteration's partials.  Returns true (uniformly in every
+// block) when the solve was already finished and nothing was updated.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
+__device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int nprev, CgCtl &s_c,
+                                             double &s_beta)
 {
-    if (a.skip && *a.skip) return;
-    // a finished solve: pass the record on and leave before any reduction
-    // (graph replays issue a fixed number of these kernels)
-    if (a.ctl[it & 1].done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
-        return;
-    }
-    __shared__ CgCtl s_c;
-    __shared__ double s_beta;
     const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;
     double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
     {
         double t[4];
-        sum_part(Pin, gridDim.x, t);
+        sum_part(Pin, nprev, t);
         if (threadIdx.x == 0) {
             double beta;
             s_c = cg_state(a.ctl[it & 1], t, it, a.rtol, a.maxit, beta);
             s_beta = beta;
             if (blockIdx.x == 0) {
                 CgCtl o = s_c;
-                if (!o.done) o.it = it + 1;   // iterations completed after this kernel
+                if (!o.done) o.it = it + 1;   // iterations completed after this one
                 a.ctl[(it + 1) & 1] = o;
             }
         }
         __syncthreads();
     }
-    if (s_c.done) return;
+    if (s_c.done) return true;
     const Geo &g = a.g;
     const int64_t S = g.S;
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
@@ -367,6 +367,91 @@ __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
     block_sum<4>(v);
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) Pout[(int64_t)blockIdx.x * 4 + q] = v[q];
+    return false;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
+{
+    if (a.skip && *a.skip) return;
+    // a finished solve: pass the record on and leave before any reduction
+    // (graph replays issue a fixed number of these kernels)
+    if (a.ctl[it & 1].done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
+        return;
+    }
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    cg_iteration<T>(a, it, gridDim.x, s_c, s_beta);
+}
+
+// Grid barrier of a cooperative launch (all blocks resident): blocks arrive
+// on one counter per group of eight (block b in group b % 8), the last of a
+// group bumps the top counter, every block waits for the top counter to
+// reach 8 * gen.  Agent-scope fences publish this block's stores (partials
+// and vectors, read by other blocks after the barrier).  The wait is bounded:
+// false if the spin limit was reached (never expected).
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned grp = blockIdx.x & 7, per = gridDim.x >> 3;
+        __threadfence();
+        const unsigned old = atomicAdd(bar + grp * kBarStride, 1u);
+        if (old + 1 == gen * per) atomicAdd(bar + 8 * kBarStride, 1u);
+        int ok = 1;
+        long spins = 0;
+        while (__hip_atomic_load(bar + 8 * kBarStride, __ATOMIC_ACQUIRE,
+                                 __HIP_MEMORY_SCOPE_AGENT) < 8u * gen) {
+            if (++spins > kSpinLimit) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// Finishes a solve that the captured iteration kernels left unfinished:
+// iterations it0, it0+1, ... in one cooperative launch, a grid barrier
+// between iterations, until the (uniform) convergence / maxit decision.
+// Ends by storing the final record in both control slots.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_tail(CgArgs<T> a, int it0, unsigned *bar)
+{
+    if (a.skip && *a.skip) return;
+    // the usual case: the captured kernels finished the solve
+    if (a.ctl[it0 & 1].done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it0 + 1) & 1] = a.ctl[it0 & 1];
+        return;
+    }
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    int nprev = a.blocks;
+    unsigned gen = 0;
+    bool ok = true;
+    for (int it = it0;; ++it) {
+        if (cg_iteration<T>(a, it, nprev, s_c, s_beta)) break;
+        nprev = gridDim.x;
+        ok = grid_barrier(bar, ++gen);
+        if (!ok) break;
+    }
+    // every block has read the control slots of its last iteration
+    if (ok) ok = grid_barrier(bar, ++gen);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        CgCtl f = s_c;
+        if (!ok) {
+            f.done = 1;
+            f.status = EC_ERR_HIP;
+        }
+        a.ctl[0] = f;
+        a.ctl[1] = f;
+    }
 }
 
 // After `iters` iteration kernels: final decision on the last iterate, the
@@ -423,6 +508,31 @@ void cg_iter(const CgArgs<T> &a, int i, hipStream_t st)
     hipLaunchKernelGGL(k_cg_iter<T>, dim3(a.blocks), dim3(kTile), 0, st, a, i);
 }
 template <typename T>
+int cg_tail_blocks()
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_tail<T>, kTile, 0) != hipSuccess ||
+        per < 1)
+        return 0;
+    const int nb = std::min(cus, cus * per) & ~7;   // one block per CU, a multiple of 8
+    return std::min(nb, kMaxBlocks);
+}
+
+template <typename T>
+hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st)
+{
+    CgArgs<T> aa = a;
+    int i0 = it0;
+    unsigned *bar = a.bar;
+    void *args[] = {&aa, &i0, &bar};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_cg_tail<T>), dim3(blocks),
+                                      dim3(kTile), args, 0, st);
+}
+
+template <typename T>
 void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_fin<T>, dim3(1), dim3(256), 0, st, a, iters);
@@ -433,6 +543,8 @@ template void cg_fin<double>(const CgArgs<double> &, int, hipStream_t);
 template void cg_init<float>(const CgArgs<float> &, hipStream_t);
 template void cg_iter<float>(const CgArgs<float> &, int, hipStream_t);
 template void cg_fin<float>(const CgArgs<float> &, int, hipStream_t);
+template int cg_tail_blocks<double>();
+template hipError_t cg_tail<double>(const CgArgs<double> &, int, int, hipStream_t);
 
 // --------------------------------------------------- FP32-refined solves
 // r = s b - K_n x in FP64, r32 = r, partials (|r|^2, |b|^2).

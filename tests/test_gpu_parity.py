@@ -328,43 +328,53 @@ def test_trajectory_nonlinear16(ec, oracle_mod):
 
 @pytest.mark.parametrize("name,method", [("c1", 2), ("nl16", 2), ("nl16", 3)])
 def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
-    """Captured steps (iteration budgets per sequence) replayed after eager
-    warm-up steps give bitwise the eager trajectory and the same PCG
-    counts; a budget below the need reports NOT_CONVERGED."""
+    """Captured steps replayed after eager warm-up steps: with iteration
+    budgets that cover every solve the trajectory is bitwise the eager one;
+    with budgets far too small the cooperative tail finishes the solves (same
+    iterates up to the order of the reductions); maxit still reports
+    NOT_CONVERGED."""
     G1, O, wl = pair(ec, oracle_mod, name)
-    G2 = ec.Problem(wl, window_cap=8)
     dt = 0.5 * 2 / O.power(iters=40)
     opts = ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10)
-    A1, A2 = G1.zeros(), G2.zeros()
-    for G, A in ((G1, A1), (G2, A2)):
-        G.set_state(A, rtol=1e-10)
+    A1 = G1.zeros()
+    G1.set_state(A1, rtol=1e-10)
     info1 = G1.info(60)
     G1.run(A1, 0, 30, dt, opts, info=info1)
-    info2 = G2.info(20)
-    G2.run(A2, 0, 10, dt, opts, info=info2)
     its = ec.info_array(info1)["iters"]
-    budget = (int(its[20::2].max()) + 2, int(its[21::2].max()) + 2)
-    gopts = ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10, graph_iters=budget)
-    G2.counters_reset()
-    g = G2.graph_capture(A2, dt, gopts)
-    for _ in range(20):
-        g.launch()
-    got = A2.cpu().numpy()
     ref = A1.cpu().numpy()
-    assert np.array_equal(got, ref)
-    c = G2.counters()
-    assert c["worst_status"] == 0 and c["steps"] == 20
-    assert c["iters_src"] + c["iters_cpl"] == int(its[20:].sum())
-    del g
-    # a budget of one iteration from rest cannot converge: reported, not hidden
+    cover = (int(its[20::2].max()) + 2, int(its[21::2].max()) + 2)
+    for budget in (cover, (1, 2)):
+        G2 = ec.Problem(wl, window_cap=8)
+        A2 = G2.zeros()
+        G2.set_state(A2, rtol=1e-10)
+        G2.run(A2, 0, 10, dt, opts)
+        G2.counters_reset()
+        g = G2.graph_capture(A2, dt, ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10,
+                                                  graph_iters=budget))
+        for _ in range(20):
+            g.launch()
+        got = A2.cpu().numpy()
+        c = G2.counters()
+        assert c["worst_status"] == 0 and c["steps"] == 20
+        n_ref = int(its[20:].sum())
+        if budget == cover:
+            assert np.array_equal(got, ref)
+            assert c["iters_src"] + c["iters_cpl"] == n_ref
+        else:
+            assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
+            assert abs(c["iters_src"] + c["iters_cpl"] - n_ref) <= max(4, n_ref // 20)
+        del g
+    # maxit below the need: reported, not hidden (also through the tail)
     A3 = G2.zeros()
     G2.set_state(A3, rtol=1e-10)
     G2.set_step(0)
     G2.counters_reset()
     g = G2.graph_capture(A3, dt, ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10,
-                                               graph_iters=(1, 1)))
+                                               maxit=5, graph_iters=(1, 1)))
     g.launch()
-    assert G2.counters()["worst_status"] == ec.EC_ERR_NOT_CONVERGED
+    c = G2.counters()
+    assert c["worst_status"] == ec.EC_ERR_NOT_CONVERGED
+    assert c["iters_cpl"] == 5
 
 
 def test_step_info_records(ec, oracle_mod):
