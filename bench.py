@@ -57,7 +57,7 @@ def method_opts(ec, name, rtol, graph_iters=(0, 0)):
     return ec.step_opts(ec.SV_ZERO, window=1, **kw)
 
 
-def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
+def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
     """`warmup` eager steps from rest (not timed; they also fill the start-vector
     histories), then `steps` replays of the captured step, continuing the same
     run, timed with events on the library's stream.  Each captured solve issues
@@ -66,12 +66,15 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
     solve still fails (maxit), the measurement is repeated with twice the
     budget."""
     import numpy as np
+    if make_opts is None:
+        def make_opts(graph_iters=(0, 0)):
+            return method_opts(ec, name, rtol, graph_iters)
     budgets = None
     for attempt in range(4):
         A = G.zeros()
         G.set_state(A, rtol=rtol)
         info = G.info(2 * warmup)
-        G.run(A, 0, warmup, dt, method_opts(ec, name, rtol), info=info)
+        G.run(A, 0, warmup, dt, make_opts(), info=info)
         its = ec.info_array(info)["iters"]
         if budgets is None:
             # typical, not worst-case, counts: a longer solve (cold start, the
@@ -79,7 +82,7 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
             h = warmup // 2
             budgets = [max(1, int(np.percentile(its[2 * h + q::2], 75)) + 2) for q in (0, 1)]
         G.counters_reset()
-        graph = G.graph_capture(A, dt, method_opts(ec, name, rtol, tuple(budgets)))
+        graph = G.graph_capture(A, dt, make_opts(tuple(budgets)))
         torch.cuda.synchronize()
         s = G.stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -106,6 +109,35 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol):
         "graph_iteration_budget": list(budgets),
         "final_state_norm": float(A.norm().item()),
     }, A
+
+
+def precision_c3(ec, torch, steps, warmup, rtol=1e-8, N=128):
+    """FP64 PCG vs FP32 inner PCG in the FP64 residual loop on the 128^3
+    Brauer grid, SPE m = 8, the same captured-step measurement as the
+    headline; the relative difference between the two final states is
+    reported (it includes the gradient part a_n may pick up)."""
+    import synth
+    G = ec.Problem(synth.nonlinear(N), window_cap=8)
+    lam = G.cfl(iters=40, rtol=1e-10)
+    dt = 0.5 * 2.0 / lam
+    out, finals = {}, {}
+    for prec, tag in ((ec.PREC_FP64, "fp64"), (ec.PREC_FP32_REFINED, "fp32_refined")):
+        def make_opts(graph_iters=(0, 0), prec=prec):
+            return ec.step_opts(ec.SV_SPE, window=8, rtol=rtol, maxit=100000, precision=prec,
+                                inner_rtol=1e-5, inner_maxit=200, outer_max=4,
+                                graph_iters=graph_iters)
+        r, A = run_method(ec, torch, G, "spe", dt, steps, warmup, rtol, make_opts)
+        out[tag] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        finals[tag] = A.clone()
+        log(f"[bench] 128^3 {tag}: {r['steps_per_s']:.1f} steps/s, {r['iters_per_step']:.2f} iters/step")
+    a64, a32 = finals["fp64"], finals["fp32_refined"]
+    out["final_state_rel_diff"] = float((a32 - a64).norm() / a64.norm())
+    out["workload"] = f"nonlinear {N}^3, {steps} captured steps after {warmup} warm-up, SPE m=8"
+    out["speedup_fp32_refined"] = round(out["fp32_refined"]["steps_per_s"] /
+                                        out["fp64"]["steps_per_s"], 3)
+    del G
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_cg_iteration(ec, torch, G, reps=400):
@@ -189,6 +221,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 FP64 / FP32-refined runs")
+    ap.add_argument("--c3-steps", type=int, default=200)
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the dominant-kernel timing and a 512 MiB device copy "
                          "(the reference for the HBM byte counters)")
@@ -258,6 +292,10 @@ def main():
             torch.cuda.empty_cache()
             log(f"[bench] probe {Np}^3: cg iteration {us:.1f} us")
 
+    c3 = None
+    if not args.no_c3:
+        c3 = precision_c3(ec, torch, args.c3_steps, args.warmup)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_steps, dt)
@@ -288,6 +326,7 @@ def main():
                         for kk, vv in v.items()} for k, v in results.items()},
         "roofline": roofline,
         "probe": extra,
+        "precision_128": c3,
         "cpu_baseline": cpu,
     }
     if "zero" in results and head != "zero":

@@ -167,10 +167,21 @@ int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y);
  * edge off the conductor).  K_n^+ b has zero divergence there, so the exact
  * solution is unchanged; the term stops the projection from amplifying the
  * gradient (null-space) part that PCG never removes from a start vector.
- * factor = 0 gives the projection as printed; the default is 1.  A change
- * empties the SPE histories.  EC_ERR_ARG for a negative or non-finite factor.
+ * factor = 0 gives the projection as printed; the default is 1.  Solves in
+ * EC_PREC_FP32_REFINED precision use 1e-6 of the weight: their solutions
+ * carry a gradient part of FP32 size, which the full weight would trade for
+ * range error.  An SPE history built with another weight starts anew at its
+ * next push or solve.  EC_ERR_ARG for a negative or non-finite factor.
  * POD (eqs. 11-14) is unaffected: its truncation drops those directions. */
 int32_t ec_set_gauge_penalty(ec_handle h, double factor);
+
+/* Linear-independence threshold of the SPE window (eq. 10 asks for linearly
+ * independent solutions without a number): a pushed solution x joins the
+ * basis only if its part orthogonal to the basis exceeds tol * ||x||.
+ * Default 1e-10 (FP64 round-off of consecutive solutions); solutions from
+ * FP32-refined solves carry FP32-level noise and want a larger value.
+ * Applies to later pushes.  EC_ERR_ARG unless 0 < tol < 1. */
+int32_t ec_set_dependency_tol(ec_handle h, double tol);
 
 /* Sequence histories (eq. 9: one history per right-hand-side sequence).
  * reset empties it; push appends a solution x (device padded array). */

@@ -22,7 +22,7 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr double kDepTol = 1e-10;   // SPE: drop a solution whose new direction is below this
+constexpr double kDepTol = 1e-10;   // SPE default: drop a solution whose new direction is below this
 constexpr int64_t kAlign = 256;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -60,6 +60,8 @@ struct ec_problem {
     // grad-div weight of the SPE projection: eta0 = half the mean diagonal of
     // K_n on edges off the conductor, scaled by the caller's factor
     double eta0 = 0.0, gauge_rel = 1.0;
+    double dep_tol = kDepTol;    // SPE linear-independence threshold (relative)
+    double seq_eta[EC_NSEQ] = {};  // grad-div weight the stored SPE matrix was built with
     // per-sequence iteration budget of the solves being captured (0 = maxit)
     int graph_iters[EC_NSEQ] = {};
     // FP32 vectors of the refinement's inner solve
@@ -427,7 +429,7 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
         h->hint[s] = 16;
     }
     HIP_TRY(h, hipStreamSynchronize(st));
-    if (!h->pin) HIP_TRY(h, hipHostMalloc((void **)&h->pin, 64, hipHostMallocDefault));
+    if (!h->pin) HIP_TRY(h, hipHostMalloc((void **)&h->pin, 128, hipHostMallocDefault));
     for (hipEvent_t &e : h->ev)
         if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->tiles = (int)((h->S + kTile - 1) / kTile);
@@ -466,6 +468,29 @@ static void seq_ensure(ec_problem *h, int seq, int method, int window, int kmax,
     h->seq_eps[seq] = eps;
 }
 
+// Grad-div weight of SPE pushes.  FP32-refined solves leave a gradient part
+// of about (iterations x FP32 epsilon) in their solutions, far above FP64
+// round-off; at the full weight the projection trades that invisible part for
+// range error the residual sees (more so on finer grids, where the ratio of
+// the largest to the smallest K_n eigenvalue grows), so those sequences use
+// 1e-6 of it: enough to damp the growth of that part, too small to bias the
+// projection.
+constexpr double kRefinedGaugeScale = 1e-6;
+
+static double spe_eta(const ec_problem *h, int precision)
+{
+    return h->gauge_rel * h->eta0 * (precision == EC_PREC_FP32_REFINED ? kRefinedGaugeScale : 1.0);
+}
+
+// an SPE history holds Q^T (K_n + eta D^T D) Q for one eta: a new weight
+// starts a new history
+static void seq_eta_ensure(ec_problem *h, int seq, int method, double eta)
+{
+    if (method != EC_SV_SPE || h->seq_eta[seq] == eta) return;
+    seq_reset(h->seq_d + seq, h->st);
+    h->seq_eta[seq] = eta;
+}
+
 static MdArgs md_args(ec_problem *h)
 {
     MdArgs m{};
@@ -494,7 +519,7 @@ static LcArgs lc_args(ec_problem *h, int seq)
 
 static void dense(ec_problem *h, int seq, int op, ec_solve_info *info = nullptr)
 {
-    small(h->seq_d + seq, op, h->part_md, kMdStride, kDepTol, info, h->st);
+    small(h->seq_d + seq, op, h->part_md, kMdStride, h->dep_tol, info, h->st);
 }
 
 // x0 and r0 = b - K_n x0 (into rb[0]) from the history of seq (eqs. 10, 14)
@@ -560,7 +585,7 @@ static void seq_push(ec_problem *h, int seq, int method, const double *x)
     spmv_slot(h->g, h->t2, h->t3, KQ, Q, &sd->slot_new, h->ld, &sd->active, st);
     // new column of Q^T (K_n + eta D^T D) Q: the grad-div term keeps the
     // projection from amplifying the gradient part of the window
-    const double eta = h->gauge_rel * h->eta0;
+    const double eta = h->seq_eta[seq];
     const double *kq = h->t3;
     if (eta > 0.0) {
         graddiv(h->g, h->t2, h->t3, h->t4, eta, &sd->active, st);
@@ -599,9 +624,11 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
     const int maxit = a.maxit;
     if (capturing(h)) {
         int budget = std::min(maxit, kGraphMaxIters);
-        const int want = hintable ? h->graph_iters[seq] : 0;
-        const bool tail = want > 0 && want < maxit && std::is_same<T, double>::value &&
-                          h->tail_blocks > 0;
+        // the sequence budget caps the FP64 solve (the tail finishes it) or
+        // each inner FP32 pass of a refined solve (the outer loop goes on)
+        const int want = h->graph_iters[seq];
+        const bool tail = hintable && want > 0 && want < maxit &&
+                          std::is_same<T, double>::value && h->tail_blocks > 0;
         if (want > 0) budget = std::min(budget, want);
         for (int i = 0; i < budget; ++i) cg_iter<T>(a, i, st);
         // rare long solves (cold start, a sudden change of the source) finish
@@ -689,11 +716,20 @@ static int32_t run_refined(ec_problem *h, int seq, const double *b, const double
     hipStream_t st = h->st;
     const int outer = o->outer_max > 0 ? o->outer_max : 8;
     refine_reset(h->ctrl_d, st);
+    const double inner_rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
+    const bool eager = !capturing(h);
     for (int pass = 0; pass <= outer; ++pass) {
         refine_residual(h->g, b, bscale, x, h->frb[0], h->part_ref, h->ctrl_d, h->cg_blocks, st);
-        refine_decide(h->part_ref, h->cg_blocks, h->ctrl_d, pass, outer, o->rtol, info,
+        refine_decide(h->part_ref, h->cg_blocks, h->ctrl_d, pass, outer, o->rtol, inner_rtol, info,
                       h->seq_d + seq, st);
         if (pass == outer) break;
+        if (eager) {
+            // stop issuing passes once the FP64 residual check has passed
+            HIP_TRY(h, hipMemcpyAsync(h->pin + 16, &h->ctrl_d->refine_done, sizeof(int),
+                                      hipMemcpyDeviceToHost, st));
+            HIP_TRY(h, hipStreamSynchronize(st));
+            if (h->pin[16]) break;
+        }
         CgArgs<float> a{};
         a.g = h->g;
         a.x = h->fd;
@@ -703,7 +739,8 @@ static int32_t run_refined(ec_problem *h, int seq, const double *b, const double
         a.bscale = nullptr;
         a.mode = START_ZERO;
         a.seq = nullptr;
-        a.rtol = o->inner_rtol > 0 ? o->inner_rtol : 1e-5;
+        a.rtol = inner_rtol;
+        a.rtol_dev = &h->ctrl_d->refine_tol;    // set by refine_decide for this pass
         a.maxit = o->inner_maxit > 0 ? o->inner_maxit : 200;
         a.ctl = h->cg_d;
         a.part = h->part_cg;
@@ -741,6 +778,7 @@ static int32_t do_solve(ec_problem *h, int seq, int method, int window, int kmax
         if (window < 1 || window > h->cap)
             return fail(h, EC_ERR_ARG, "window must be 1..%d (the bound window_cap)", h->cap);
         seq_ensure(h, seq, method, window, kmax, eps);
+        seq_eta_ensure(h, seq, method, spe_eta(h, o->precision));
         seq_start(h, seq, method, b, bscale, x, info);
         mode = START_DEV;
     } else {
@@ -780,13 +818,17 @@ extern "C" int32_t ec_set_gauge_penalty(ec_handle h, double factor)
     NEED_BOUND(h);
     if (!(factor >= 0.0) || !std::isfinite(factor))
         return fail(h, EC_ERR_ARG, "factor must be finite and >= 0");
-    if (factor != h->gauge_rel) {
-        // stored projected matrices hold the old weight: start SPE histories anew
-        for (int s = 0; s < EC_NSEQ; ++s)
-            if (h->seq_method[s] == EC_SV_SPE) seq_reset(h->seq_d + s, h->st);
-        h->gauge_rel = factor;
-    }
-    return launch_check(h, "gauge penalty");
+    // histories built with another weight start anew at their next use
+    h->gauge_rel = factor;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_set_dependency_tol(ec_handle h, double tol)
+{
+    NEED_BOUND(h);
+    if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, EC_ERR_ARG, "tol must be in (0, 1)");
+    h->dep_tol = tol;
+    return EC_OK;
 }
 
 extern "C" int32_t ec_history_reset(ec_handle h, int32_t seq)
@@ -811,6 +853,7 @@ extern "C" int32_t ec_history_push(ec_handle h, int32_t seq, int32_t method, int
     const double eps = (h->seq_method[seq] == method && h->seq_win[seq] == window)
                            ? h->seq_eps[seq] : 1e-4;
     seq_ensure(h, seq, method, window, kmax, eps);
+    seq_eta_ensure(h, seq, method, spe_eta(h, EC_PREC_FP64));
     seq_push(h, seq, method, x);
     return launch_check(h, "history push");
 }
@@ -1049,8 +1092,10 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     if (opts->graph_iters[0] < 0 || opts->graph_iters[1] < 0)
         return fail(h, EC_ERR_ARG, "graph_iters must be >= 0");
     // configure the histories eagerly so that no reset is recorded
-    for (int s : {EC_SEQ_SRC, EC_SEQ_CPL})
+    for (int s : {EC_SEQ_SRC, EC_SEQ_CPL}) {
         seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
+        seq_eta_ensure(h, s, opts->start_method, spe_eta(h, opts->solve.precision));
+    }
     HIP_TRY(h, hipStreamSynchronize(h->st));
     hipGraph_t graph = nullptr;
     HIP_TRY(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));

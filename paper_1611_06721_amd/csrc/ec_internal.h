@@ -83,6 +83,7 @@ struct Ctrl {
     int refine_done;         // FP32-refined outer loop finished flag
     int refine_zero;         // the right-hand side was zero
     double refine_rr, refine_bb;
+    double refine_tol;       // relative tolerance of the next inner FP32 solve
 };
 
 // ----------------------------------------------------------------- launchers
@@ -127,6 +128,7 @@ struct CgArgs {
     int mode;                // START_*
     const SeqDev *seq;       // START_DEV reads seq->zero_start; basis info
     double rtol;
+    const double *rtol_dev;  // device tolerance read at the first iteration (nullptr: rtol)
     int maxit;
     CgCtl *ctl;              // [2]
     double *part;            // [2][blocks][4]
@@ -242,7 +244,8 @@ void mask_copy(const Geo &g, const double *x, double *y, int cls_keep, hipStream
 void refine_residual(const Geo &g, const double *b, const double *bscale, const double *x,
                      float *r32, double *part, const Ctrl *ctrl, int blocks, hipStream_t st);
 void refine_decide(const double *part, int blocks, Ctrl *ctrl, int pass, int outer_max,
-                   double rtol, ec_solve_info *info, const SeqDev *seq, hipStream_t st);
+                   double rtol, double inner_rtol, ec_solve_info *info, const SeqDev *seq,
+                   hipStream_t st);
 void refine_update(double *x, const float *d, const Ctrl *ctrl, int64_t n, hipStream_t st);
 void refine_final(double *x, const Ctrl *ctrl, int64_t n, hipStream_t st);
 void refine_reset(Ctrl *ctrl, hipStream_t st);

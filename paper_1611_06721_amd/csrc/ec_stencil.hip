@@ -309,7 +309,8 @@ __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int npr
         sum_part(Pin, nprev, t);
         if (threadIdx.x == 0) {
             double beta;
-            s_c = cg_state(a.ctl[it & 1], t, it, a.rtol, a.maxit, beta);
+            const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
+            s_c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
             s_beta = beta;
             if (blockIdx.x == 0) {
                 CgCtl o = s_c;
@@ -465,7 +466,8 @@ __global__ void __launch_bounds__(256) k_cg_fin(CgArgs<T> a, int iters)
     if (threadIdx.x != 0) return;
     double beta;
     // maxit + 1 lets the last iterate be judged on its residual only
-    CgCtl c = cg_state(a.ctl[iters & 1], t, iters, a.rtol, a.maxit + 1, beta);
+    const double rtol = (iters == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
+    CgCtl c = cg_state(a.ctl[iters & 1], t, iters, rtol, a.maxit + 1, beta);
     int st = c.status;
     if (!c.done) st = EC_ERR_NOT_CONVERGED;
     const int it = c.it;
@@ -493,7 +495,9 @@ __global__ void __launch_bounds__(256) k_cg_fin(CgArgs<T> a, int iters)
     }
     if (a.ctrl) {
         a.ctrl->iters[a.seq_id] += it;
-        if (st < a.ctrl->worst) a.ctrl->worst = st;
+        // an inner solve of the refinement loop may stop at its cap: only the
+        // outer FP64 residual check decides the status
+        if (!a.accum && st < a.ctrl->worst) a.ctrl->worst = st;
     }
 }
 
@@ -589,7 +593,7 @@ void refine_residual(const Geo &g, const double *b, const double *bscale, const 
 // Converged (||r|| <= rtol ||b||), out of passes, or another inner solve.
 __global__ void __launch_bounds__(256)
     k_refine_decide(const double *part, int nb, Ctrl *ctrl, int pass, int outer_max, double rtol,
-                    ec_solve_info *info, const SeqDev *seq)
+                    double inner_rtol, ec_solve_info *info, const SeqDev *seq)
 {
     if (ctrl->refine_done) return;
     double s[2];
@@ -628,13 +632,18 @@ __global__ void __launch_bounds__(256)
     }
     ctrl->refine_rr = rr;
     ctrl->refine_bb = bb2;
+    // the inner solve only has to bring the residual below half the target:
+    // relative reduction 0.5 rtol / rel, never looser than 0.5 nor tighter
+    // than the caller's inner_rtol (FP32 limits what it can reach)
+    ctrl->refine_tol = rel > 0.0 ? fmax(inner_rtol, fmin(0.5, 0.5 * rtol / rel)) : inner_rtol;
 }
 
 void refine_decide(const double *part, int blocks, Ctrl *ctrl, int pass, int outer_max,
-                   double rtol, ec_solve_info *info, const SeqDev *seq, hipStream_t st)
+                   double rtol, double inner_rtol, ec_solve_info *info, const SeqDev *seq,
+                   hipStream_t st)
 {
     hipLaunchKernelGGL(k_refine_decide, dim3(1), dim3(256), 0, st, part, blocks, ctrl, pass,
-                       outer_max, rtol, info, seq);
+                       outer_max, rtol, inner_rtol, info, seq);
 }
 
 // x += d (FP32 correction) unless the loop has finished; b = 0 gives x = 0

@@ -131,6 +131,10 @@ class Problem:
         with self._on_stream():
             self._chk(self.lib.ec_set_gauge_penalty(self.h, factor))
 
+    def set_dependency_tol(self, tol):
+        with self._on_stream():
+            self._chk(self.lib.ec_set_dependency_tol(self.h, tol))
+
     def history_reset(self, seq):
         with self._on_stream():
             self._chk(self.lib.ec_history_reset(self.h, seq))
