@@ -11,6 +11,8 @@ Contents
   explicit Euler of eqs. (5a)-(7), power method for eq. (8), adjoint.
 * ``startvec.py``: SPE (eq. 10, modified Gram-Schmidt) and POD (eqs. 11-14,
   SVD of the snapshot matrix) start vectors, written from Sec. III.
+* ``adjoint.py``: the discrete adjoint of the explicit Euler loop (Joule
+  loss, gradients with respect to sigma and k1).
 * ``dense.py``: dense matrices of tiny grids for the pins (pseudo-inverse by
   eigendecomposition, Schur complement, closed-form decay).
 """
@@ -82,6 +84,10 @@ def lib():
                          C.c_void_p, C.c_void_p]
     L.or_power.restype = C.c_double
     L.or_power.argtypes = [C.c_void_p, _dp, C.c_int, C.c_double, C.c_uint]
+    L.or_jn.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.or_jnT.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.or_dn_dk1.argtypes = [C.c_void_p, _dp, C.c_int, _dp]
+    L.or_dmsig.argtypes = [C.c_void_p, C.c_int, _dp]
     L.or_set_threads.argtypes = [C.c_int]
     L.or_get_threads.restype = C.c_int
     _lib = L
@@ -203,6 +209,41 @@ class Problem:
     def power(self, A=None, iters=60, rtol=1e-12, seed=1):
         A = np.zeros(self.n_pad) if A is None else np.ascontiguousarray(A, np.float64)
         return lib().or_power(self._h, A, iters, rtol, seed)
+
+    # -- adjoint pieces ------------------------------------------------------
+    def n_c(self, a):
+        """N(a) = [K(nu(a)) a]_C for a restricted to C (the conducting block)."""
+        ac = np.where(self.C, a, 0.0)
+        return np.where(self.C, self.apply(ac, ac), 0.0)
+
+    def jn(self, a, v):
+        y = np.zeros(self.n_pad)
+        lib().or_jn(self._h, np.ascontiguousarray(a, np.float64),
+                    np.ascontiguousarray(v, np.float64), y)
+        return y
+
+    def jnT(self, a, lam):
+        y = np.zeros(self.n_pad)
+        lib().or_jnT(self._h, np.ascontiguousarray(a, np.float64),
+                     np.ascontiguousarray(lam, np.float64), y)
+        return y
+
+    def dn_dk1(self, a, mat=1):
+        y = np.zeros(self.n_pad)
+        lib().or_dn_dk1(self._h, np.ascontiguousarray(a, np.float64), int(mat), y)
+        return y
+
+    def dmsig(self, mat=1):
+        y = np.zeros(self.n_pad)
+        lib().or_dmsig(self._h, int(mat), y)
+        return y
+
+    def schur(self, w, rtol=1e-12):
+        """S w = K_cn K_n^+ K_cn^T w on C edges (w read on C)."""
+        s, _, _, st = self.cg(self.kcnT(np.where(self.C, w, 0.0)), rtol=rtol)
+        if st:
+            raise RuntimeError(f"oracle CG failed with status {st}")
+        return np.where(self.C, self.apply(np.where(self.N, s, 0.0), np.zeros(self.n_pad)), 0.0)
 
 
 def set_threads(n):

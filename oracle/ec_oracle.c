@@ -566,3 +566,239 @@ double or_power(void *h, const double *A, int iters, double rtol, unsigned seed)
     free(vc); free(Ks); free(nu_frozen); free(w.sj);
     return lam;
 }
+
+/* ------------------------------------------------------------- adjoint */
+/*
+ * Pieces of the discrete adjoint of the time loop.  With the conducting
+ * block N(a) = [C^T M_nu(a) C a]_C (a on C edges, the reluctivity of the iron
+ * cells taken from a through their cell B), one step is
+ *   F(a) = a - dt M_c^{-1} [ N(a) - S a + K_cn K_n^+ j ],  S = K_cn K_n^+ K_cn^T,
+ * and the adjoint needs J_N(a)^T, dN/dk1 and dM_c/dsigma.  J_N is not
+ * symmetric (face-averaged nu), so its transpose is written out.
+ */
+
+/* geometric part of the face reluctance: dual edge length / face area */
+static double face_geo(const orp *p, int c)
+{
+    if (c == 0) return p->hx / (p->hy * p->hz);
+    if (c == 1) return p->hy / (p->hz * p->hx);
+    return p->hz / (p->hx * p->hy);
+}
+
+static double face_area(const orp *p, int c)
+{
+    if (c == 0) return p->hy * p->hz;
+    if (c == 1) return p->hz * p->hx;
+    return p->hx * p->hy;
+}
+
+/* does face (c,i,j,k) exist, and the two cells whose nu it averages */
+static int face_cells(const orp *p, int c, long i, long j, long k, long *ca, long *cb)
+{
+    if (c == 0) {
+        if (!(j < p->ny && k < p->nz)) return 0;
+        long i0 = i > 0 ? i - 1 : i, i1 = i < p->nx ? i : i - 1;
+        *ca = CI(p, i0, j, k); *cb = CI(p, i1, j, k);
+    } else if (c == 1) {
+        if (!(k < p->nz && i < p->nx)) return 0;
+        long j0 = j > 0 ? j - 1 : j, j1 = j < p->ny ? j : j - 1;
+        *ca = CI(p, i, j0, k); *cb = CI(p, i, j1, k);
+    } else {
+        if (!(i < p->nx && j < p->ny)) return 0;
+        long k0 = k > 0 ? k - 1 : k, k1 = k < p->nz ? k : k - 1;
+        *ca = CI(p, i, j, k0); *cb = CI(p, i, j, k1);
+    }
+    return 1;
+}
+
+/* y = C^T f on every edge, then restricted to C edges */
+static void curlT_c(const orp *p, const double *hf, double *y)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    for (long k = 0; k <= nz; ++k)
+    for (long j = 0; j <= ny; ++j)
+    for (long i = 0; i <= nx; ++i) {
+        long ex = EI(p, 0, i, j, k), ey = EI(p, 1, i, j, k), ez = EI(p, 2, i, j, k);
+        y[ex] = (p->cls[ex] != CLS_C) ? 0.0
+              : hf[EI(p, 2, i, j, k)] - hf[EI(p, 2, i, j - 1, k)]
+                - hf[EI(p, 1, i, j, k)] + hf[EI(p, 1, i, j, k - 1)];
+        y[ey] = (p->cls[ey] != CLS_C) ? 0.0
+              : hf[EI(p, 0, i, j, k)] - hf[EI(p, 0, i, j, k - 1)]
+                - hf[EI(p, 2, i, j, k)] + hf[EI(p, 2, i - 1, j, k)];
+        y[ez] = (p->cls[ez] != CLS_C) ? 0.0
+              : hf[EI(p, 1, i, j, k)] - hf[EI(p, 1, i - 1, j, k)]
+                - hf[EI(p, 0, i, j, k)] + hf[EI(p, 0, i, j - 1, k)];
+    }
+}
+
+/* the C-edge part of a (zero elsewhere) */
+static double *c_part(const orp *p, const double *a)
+{
+    double *o = malloc(p->npad * sizeof(double));
+    for (long e = 0; e < p->npad; ++e) o[e] = p->cls[e] == CLS_C ? a[e] : 0.0;
+    return o;
+}
+
+/* dnu/ds of cell c at s = |B|^2 (Brauer: k1 k2 exp(k2 s)) */
+static double dnu_ds(const orp *p, long c, double s)
+{
+    int m = p->cmat[c];
+    if (m == 0) return 0.0;
+    return p->k1[m] * p->k2[m] * exp(p->k2[m] * s);
+}
+
+/* y = J_N(a) v on C edges: the derivative of N along v (a, v read on C). */
+void or_jn(void *h, const double *a, const double *v, double *y)
+{
+    orp *p = h;
+    const long n = p->npad;
+    double *ac = c_part(p, a), *vc = c_part(p, v);
+    double *fa = malloc(n * sizeof(double)), *fv = malloc(n * sizeof(double));
+    double *hf = calloc(n, sizeof(double)), *dnu = calloc(p->ncell, sizeof(double));
+    nu_from(p, ac);
+    curl(p, ac, fa);
+    curl(p, vc, fv);
+    for (long k = 0; k < p->nz; ++k)
+    for (long j = 0; j < p->ny; ++j)
+    for (long i = 0; i < p->nx; ++i) {
+        long c = CI(p, i, j, k);
+        if (p->cmat[c] == 0) continue;
+        double B[3], dB[3];
+        cell_B(p, fa, i, j, k, B);
+        cell_B(p, fv, i, j, k, dB);
+        double s = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        dnu[c] = dnu_ds(p, c, s) * 2.0 * (B[0] * dB[0] + B[1] * dB[1] + B[2] * dB[2]);
+    }
+    for (int d = 0; d < 3; ++d)
+    for (long k = 0; k <= p->nz; ++k)
+    for (long j = 0; j <= p->ny; ++j)
+    for (long i = 0; i <= p->nx; ++i) {
+        long ca, cb;
+        if (!face_cells(p, d, i, j, k, &ca, &cb)) continue;
+        long f = EI(p, d, i, j, k);
+        hf[f] = face_w(p, d, i, j, k) * fv[f]
+              + face_geo(p, d) * 0.5 * (dnu[ca] + dnu[cb]) * fa[f];
+    }
+    curlT_c(p, hf, y);
+    free(ac); free(vc); free(fa); free(fv); free(hf); free(dnu);
+}
+
+/* y = J_N(a)^T lam on C edges (a, lam read on C). */
+void or_jnT(void *h, const double *a, const double *lam, double *y)
+{
+    orp *p = h;
+    const long n = p->npad;
+    double *ac = c_part(p, a), *lc = c_part(p, lam);
+    double *fa = malloc(n * sizeof(double)), *fl = malloc(n * sizeof(double));
+    double *hf = calloc(n, sizeof(double));
+    double *acc = calloc(p->ncell, sizeof(double));
+    nu_from(p, ac);
+    curl(p, ac, fa);
+    curl(p, lc, fl);
+    /* acc_c = sum over the (face, side) pairs with side cell c of w_f (C lam)_f (C a)_f */
+    for (int d = 0; d < 3; ++d)
+    for (long k = 0; k <= p->nz; ++k)
+    for (long j = 0; j <= p->ny; ++j)
+    for (long i = 0; i <= p->nx; ++i) {
+        long ca, cb;
+        if (!face_cells(p, d, i, j, k, &ca, &cb)) continue;
+        long f = EI(p, d, i, j, k);
+        double t = face_geo(p, d) * fl[f] * fa[f];
+        acc[ca] += t;
+        acc[cb] += t;
+    }
+    /* gamma_c = nu'(s_c) acc_c; q on the six faces of c: gamma_c B_c[dir] / (2 area) */
+    for (long k = 0; k < p->nz; ++k)
+    for (long j = 0; j < p->ny; ++j)
+    for (long i = 0; i < p->nx; ++i) {
+        long c = CI(p, i, j, k);
+        if (p->cmat[c] == 0) continue;
+        double B[3];
+        cell_B(p, fa, i, j, k, B);
+        double s = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        double g = dnu_ds(p, c, s) * acc[c];
+        if (g == 0.0) continue;
+        hf[EI(p, 0, i, j, k)] += g * 0.5 * B[0] / face_area(p, 0);
+        hf[EI(p, 0, i + 1, j, k)] += g * 0.5 * B[0] / face_area(p, 0);
+        hf[EI(p, 1, i, j, k)] += g * 0.5 * B[1] / face_area(p, 1);
+        hf[EI(p, 1, i, j + 1, k)] += g * 0.5 * B[1] / face_area(p, 1);
+        hf[EI(p, 2, i, j, k)] += g * 0.5 * B[2] / face_area(p, 2);
+        hf[EI(p, 2, i, j, k + 1)] += g * 0.5 * B[2] / face_area(p, 2);
+    }
+    /* plus the symmetric part M_nu C lam */
+    for (int d = 0; d < 3; ++d)
+    for (long k = 0; k <= p->nz; ++k)
+    for (long j = 0; j <= p->ny; ++j)
+    for (long i = 0; i <= p->nx; ++i) {
+        long ca, cb;
+        if (!face_cells(p, d, i, j, k, &ca, &cb)) continue;
+        long f = EI(p, d, i, j, k);
+        hf[f] += face_w(p, d, i, j, k) * fl[f];
+    }
+    curlT_c(p, hf, y);
+    free(ac); free(lc); free(fa); free(fl); free(hf); free(acc);
+}
+
+/* y = dN/dk1 of material mat at a (on C edges): C^T diag(dM_nu/dk1) C a with
+ * dM_nu,f/dk1 = w_f * mean over the face's two cells of exp(k2 s_c)
+ * (cells of material mat; zero for the others). */
+void or_dn_dk1(void *h, const double *a, int mat, double *y)
+{
+    orp *p = h;
+    const long n = p->npad;
+    double *ac = c_part(p, a);
+    double *fa = malloc(n * sizeof(double)), *hf = calloc(n, sizeof(double));
+    double *e = calloc(p->ncell, sizeof(double));
+    curl(p, ac, fa);
+    for (long k = 0; k < p->nz; ++k)
+    for (long j = 0; j < p->ny; ++j)
+    for (long i = 0; i < p->nx; ++i) {
+        long c = CI(p, i, j, k);
+        if (p->cmat[c] != mat || mat == 0) continue;
+        double B[3];
+        cell_B(p, fa, i, j, k, B);
+        e[c] = exp(p->k2[mat] * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
+    }
+    for (int d = 0; d < 3; ++d)
+    for (long k = 0; k <= p->nz; ++k)
+    for (long j = 0; j <= p->ny; ++j)
+    for (long i = 0; i <= p->nx; ++i) {
+        long ca, cb;
+        if (!face_cells(p, d, i, j, k, &ca, &cb)) continue;
+        long f = EI(p, d, i, j, k);
+        hf[f] = face_geo(p, d) * 0.5 * (e[ca] + e[cb]) * fa[f];
+    }
+    curlT_c(p, hf, y);
+    free(ac); free(fa); free(hf); free(e);
+}
+
+/* dM_sigma/dsigma of material mat on every edge (zero off C): the quarter
+ * dual faces of the edge's cells of that material over the edge length. */
+void or_dmsig(void *h, int mat, double *y)
+{
+    orp *p = h;
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    memset(y, 0, p->npad * sizeof(double));
+    for (long k = 0; k <= nz; ++k)
+    for (long j = 0; j <= ny; ++j)
+    for (long i = 0; i <= nx; ++i) {
+        if (i < nx && p->cls[EI(p, 0, i, j, k)] == CLS_C) {
+            int cnt = 0;
+            for (long dj = -1; dj <= 0; ++dj) for (long dk = -1; dk <= 0; ++dk)
+                cnt += p->cmat[CI(p, i, j + dj, k + dk)] == mat;
+            y[EI(p, 0, i, j, k)] = cnt * (p->hy * p->hz / 4.0) / p->hx;
+        }
+        if (j < ny && p->cls[EI(p, 1, i, j, k)] == CLS_C) {
+            int cnt = 0;
+            for (long di = -1; di <= 0; ++di) for (long dk = -1; dk <= 0; ++dk)
+                cnt += p->cmat[CI(p, i + di, j, k + dk)] == mat;
+            y[EI(p, 1, i, j, k)] = cnt * (p->hz * p->hx / 4.0) / p->hy;
+        }
+        if (k < nz && p->cls[EI(p, 2, i, j, k)] == CLS_C) {
+            int cnt = 0;
+            for (long di = -1; di <= 0; ++di) for (long dj = -1; dj <= 0; ++dj)
+                cnt += p->cmat[CI(p, i + di, j + dj, k)] == mat;
+            y[EI(p, 2, i, j, k)] = cnt * (p->hx * p->hy / 4.0) / p->hz;
+        }
+    }
+}
