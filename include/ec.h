@@ -241,6 +241,47 @@ int32_t ec_counters_reset(ec_handle h);
 int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, double rtol,
                double *lambda_max);
 
+/* Replace material mat_id (1..n_mats) of the handle: conductivity and
+ * Brauer coefficients (eq. 1).  M_sigma of the conducting edges is rebuilt;
+ * the conducting edge set, K_n and the start-vector histories stay valid
+ * (sigma must stay positive).  A dt from ec_cfl may no longer be stable.
+ * Synchronises.  EC_ERR_ARG for a bad id or values. */
+int32_t ec_set_material(ec_handle h, int32_t mat_id, const ec_material *m);
+
+/* Discrete adjoint of the time loop (eqs. 6-7, sign of eq. 5a) for the
+ * Joule loss of the conductor
+ *     L = sum_{m=1..n_steps} (1/dt) d_m^T M_c d_m,   d_m = a_c^m - a_c^{m-1},
+ * and its gradient with respect to the conductivity sigma and the Brauer
+ * coefficient k1 of one material.  With mu_m = dL/da_c^m:
+ *     mu_M = (2/dt) M_c d_M,
+ *     mu_m = (2/dt) M_c (d_m - d_{m+1}) + mu_{m+1} - dt [J_N(a^m)^T - S] M_c^{-1} mu_{m+1},
+ * N(a) = [C^T M_nu(a) C a]_C, S = K_cn K_n^+ K_cn^T (one K_n^+ solve per
+ * step on sequence EC_SEQ_ADJ with the step options' start vector), and
+ *     dL/dsigma = sum_m [(1/dt) d_m^T Phi d_m - mu_m^T M_c^{-1} Phi d_m],
+ *     dL/dk1    = -dt sum_m mu_m^T M_c^{-1} dN/dk1(a^{m-1}),   Phi = dM_c/dsigma.
+ *
+ * ec_adjoint_sizes: bytes of the caller-owned device workspace for n_steps
+ * steps with a checkpoint every checkpoint_every steps (one per segment:
+ * a_c, s_c, s_j and the source / coupling histories, so that a recomputed
+ * segment is bitwise the forward one).
+ * ec_adjoint_forward: a^0 from A (conducting part; like ec_set_state), then
+ * steps 1..n_steps (ec_step semantics, eager), writing the checkpoints and
+ * *loss (device double).  A holds a^M on return.
+ * ec_adjoint_backward: with the same workspace, n_steps, checkpoint_every and
+ * dt as the last forward call (EC_ERR_STATE otherwise), recomputes each
+ * segment from its checkpoint (last first) and runs the adjoint recursion;
+ * grads (device double[2]) = {dL/dsigma, dL/dk1} of material mat_id.  It
+ * leaves the stepping state of a recomputed segment behind: call
+ * ec_set_state before stepping again.  EC_ERR_ARG for bad sizes, ids or a
+ * workspace below ec_adjoint_sizes. */
+int32_t ec_adjoint_sizes(ec_handle h, int64_t n_steps, int32_t checkpoint_every, int64_t *bytes);
+int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt, int32_t checkpoint_every,
+                           const ec_step_opts *opts, void *adj_ws, int64_t adj_bytes, double *A,
+                           double *loss);
+int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt, int32_t checkpoint_every,
+                            const ec_step_opts *opts, void *adj_ws, int64_t adj_bytes,
+                            int32_t mat_id, double *grads);
+
 /* HIP graph of one step (device step counter, fixed dt and opts) captured on
  * the bound stream; launch replays it on `hip_stream`. */
 int32_t ec_graph_capture_step(ec_handle h, double dt, double *A, const ec_step_opts *opts,

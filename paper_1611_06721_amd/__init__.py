@@ -17,4 +17,7 @@ def __getattr__(name):
     if name in ("Problem", "Graph", "solve_opts", "step_opts", "info_array", "INFO_BYTES"):
         from . import problem
         return getattr(problem, name)
+    if name in ("EddyLoss", "eddy_loss"):
+        from . import autograd
+        return getattr(autograd, name)
     raise AttributeError(name)

@@ -90,6 +90,12 @@ SIGNATURES = {
     "ec_counters_reset": (C.c_int32, [_H]),
     "ec_set_step": (C.c_int32, [_H, C.c_int64]),
     "ec_cfl": (C.c_int32, [_H, _P, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "ec_set_material": (C.c_int32, [_H, C.c_int32, C.POINTER(Material)]),
+    "ec_adjoint_sizes": (C.c_int32, [_H, C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
+    "ec_adjoint_forward": (C.c_int32, [_H, C.c_int64, C.c_double, C.c_int32, C.POINTER(StepOpts),
+                                       _P, C.c_int64, _P, _P]),
+    "ec_adjoint_backward": (C.c_int32, [_H, C.c_int64, C.c_double, C.c_int32,
+                                        C.POINTER(StepOpts), _P, C.c_int64, C.c_int32, _P]),
     "ec_graph_capture_step": (C.c_int32, [_H, C.c_double, _P, C.POINTER(StepOpts), _P,
                                           C.POINTER(C.c_void_p)]),
     "ec_graph_launch": (C.c_int32, [_P, _P]),

@@ -64,6 +64,11 @@ struct ec_problem {
     double seq_eta[EC_NSEQ] = {};  // grad-div weight the stored SPE matrix was built with
     // per-sequence iteration budget of the solves being captured (0 = maxit)
     int graph_iters[EC_NSEQ] = {};
+    // the adjoint workspace the last forward pass filled (checkpoints)
+    const void *adj_ws = nullptr;
+    int64_t adj_steps = 0;
+    int adj_every = 0;
+    double adj_dt = 0.0;
     // FP32 vectors of the refinement's inner solve
     float *frb[2] = {}, *fwb[2] = {}, *fsb[2] = {}, *fpv = nullptr, *fd = nullptr;
     double *hist[EC_NSEQ] = {};
@@ -966,10 +971,17 @@ extern "C" int32_t ec_run(ec_handle h, int64_t m0, int64_t nsteps, double dt, do
     return EC_OK;
 }
 
+static int32_t set_state_impl(ec_problem *h, const double *A, const ec_solve_opts *opts);
+
 extern "C" int32_t ec_set_state(ec_handle h, const double *A, const ec_solve_opts *opts)
 {
     NEED_BOUND(h);
     if (!aligned(A) || !opts) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
+    return set_state_impl(h, A, opts);
+}
+
+static int32_t set_state_impl(ec_problem *h, const double *A, const ec_solve_opts *opts)
+{
     hipStream_t st = h->st;
     fill(h->ac, 0.0, h->npad, st);
     copy_c(h->cslot_d, h->nc, A, h->ac, st);
@@ -1081,6 +1093,310 @@ extern "C" int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, dou
 }
 
 // ------------------------------------------------------------ graphs
+
+// ------------------------------------------------------------ materials
+// M_sigma of every conducting edge from the current material table (the
+// conducting edge set itself is fixed at create: sigma stays positive).
+static void conductivities(ec_problem *h, const int *mat_filter, std::vector<double> *out)
+{
+    const int nx = h->g.nx, ny = h->g.ny;
+    const double hh[3] = {h->g.hx, h->g.hy, h->g.hz};
+    out->assign(h->nc, 0.0);
+    for (int t = 0; t < h->nc; ++t) {
+        const int64_t e = h->cslot[t];
+        const int c = (int)(e / h->S);
+        const int64_t nd = e - (int64_t)c * h->S;
+        const int i = (int)(nd % (nx + 1)), j = (int)((nd / (nx + 1)) % (ny + 1));
+        const int k = (int)(nd / ((int64_t)(nx + 1) * (ny + 1)));
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        const double quarter = hh[a1] * hh[a2] / 4.0 / hh[c];
+        double sum = 0.0;
+        for (int d1 = -1; d1 <= 0; ++d1)
+            for (int d2 = -1; d2 <= 0; ++d2) {
+                int cc[3] = {i, j, k};
+                cc[a1] += d1;
+                cc[a2] += d2;
+                const int m = h->cmat[((int64_t)cc[2] * ny + cc[1]) * nx + cc[0]];
+                if (mat_filter) sum += (m == *mat_filter) ? 1.0 : 0.0;
+                else sum += h->mats.sig[m];
+            }
+        (*out)[t] = sum * quarter;
+    }
+}
+
+extern "C" int32_t ec_set_material(ec_handle h, int32_t mat_id, const ec_material *m)
+{
+    NEED_BOUND(h);
+    if (mat_id < 1 || mat_id >= h->mats.n || !m)
+        return fail(h, EC_ERR_ARG, "mat_id must be 1..%d", h->mats.n - 1);
+    if (!(m->sigma > 0) || !std::isfinite(m->sigma) || !(m->k1 >= 0) || !std::isfinite(m->k1) ||
+        !std::isfinite(m->k2) || !(m->k3 > 0) || !std::isfinite(m->k3))
+        return fail(h, EC_ERR_ARG, "need sigma > 0, k1 >= 0, k3 > 0 and finite k2");
+    h->mats.sig[mat_id] = m->sigma;
+    h->mats.k1[mat_id] = m->k1;
+    h->mats.k2[mat_id] = m->k2;
+    h->mats.k3[mat_id] = m->k3;
+    std::vector<double> ms;
+    conductivities(h, nullptr, &ms);
+    for (int t = 0; t < h->nc; ++t) h->minv[t] = 1.0 / ms[t];
+    hipStream_t st = h->st;
+    HIP_TRY(h, hipMemcpyAsync(h->mats_d, &h->mats, sizeof(Mats), hipMemcpyHostToDevice, st));
+    if (h->nc)
+        HIP_TRY(h, hipMemcpyAsync(h->minv_d, h->minv.data(), (size_t)h->nc * 8,
+                                  hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    return EC_OK;
+}
+
+// -------------------------------------------------------------- adjoint
+// Workspace of a forward/backward pair: one checkpoint per segment of
+// `every` steps (a_c, s_c, s_j, and the source and coupling histories with
+// their small-matrix state, so that a recomputed segment is bitwise the
+// forward one), the states of one segment, and the adjoint's own vectors.
+struct AdjWs {
+    int64_t n_ckpt = 0, ck_bytes = 0, hist_bytes = 0;
+    char *ck = nullptr;
+    double *seg = nullptr;                                   // (every+1) x nc
+    double *mu_a = nullptr, *mu_b = nullptr, *dnext = nullptr, *jt = nullptr, *phi = nullptr;
+    double *wpad = nullptr, *apad = nullptr, *upad = nullptr, *badj = nullptr, *sadj = nullptr;
+    double *aseg = nullptr, *cellv = nullptr, *part = nullptr, *acc = nullptr;
+};
+
+static int64_t adj_layout(const ec_problem *h, int64_t M, int every, char *base, AdjWs *w)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        const int64_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return base ? base + o : nullptr;
+    };
+    const int64_t ld = align_up(h->npad, 64), nc = std::max(h->nc, 1);
+    w->n_ckpt = (M + every - 1) / every;
+    w->hist_bytes = 2 * (int64_t)(h->cap + 1) * ld * 8;
+    w->ck_bytes = align_up(nc * 8, kAlign) + 2 * ld * 8 + 2 * align_up(sizeof(SeqDev), kAlign) +
+                  2 * w->hist_bytes;
+    w->ck = take(w->n_ckpt * w->ck_bytes);
+    w->seg = (double *)take((int64_t)(every + 1) * nc * 8);
+    double **cvec[] = {&w->mu_a, &w->mu_b, &w->dnext, &w->jt, &w->phi};
+    for (double **v : cvec) *v = (double *)take(nc * 8);
+    double **pvec[] = {&w->wpad, &w->apad, &w->upad, &w->badj, &w->sadj, &w->aseg};
+    for (double **v : pvec) *v = (double *)take(ld * 8);
+    w->cellv = (double *)take(h->ncell * 5 * 8);
+    w->part = (double *)take((std::max<int64_t>(h->ncell, nc) / 256 + 2) * 8);
+    w->acc = (double *)take(4 * 8);
+    return off;
+}
+
+struct CkPtrs {
+    double *ac, *sc, *sj;
+    SeqDev *seq[2];
+    double *hist[2];
+};
+
+static CkPtrs ckpt(const ec_problem *h, const AdjWs &w, int64_t k)
+{
+    const int64_t ld = align_up(h->npad, 64), nc = std::max(h->nc, 1);
+    char *p = w.ck + k * w.ck_bytes;
+    CkPtrs c{};
+    c.ac = (double *)p;
+    p += align_up(nc * 8, kAlign);
+    c.sc = (double *)p;
+    p += ld * 8;
+    c.sj = (double *)p;
+    p += ld * 8;
+    for (int q = 0; q < 2; ++q) {
+        c.seq[q] = (SeqDev *)p;
+        p += align_up(sizeof(SeqDev), kAlign);
+    }
+    for (int q = 0; q < 2; ++q) {
+        c.hist[q] = (double *)p;
+        p += w.hist_bytes;
+    }
+    return c;
+}
+
+static int32_t ckpt_copy(ec_problem *h, const AdjWs &w, int64_t k, const double *ac, bool save)
+{
+    const CkPtrs c = ckpt(h, w, k);
+    hipStream_t st = h->st;
+    const size_t vb = (size_t)h->npad * 8;
+    const int seqs[2] = {EC_SEQ_SRC, EC_SEQ_CPL};
+    if (save) {
+        if (h->nc)
+            HIP_TRY(h, hipMemcpyAsync(c.ac, ac, (size_t)h->nc * 8, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(h, hipMemcpyAsync(c.sc, h->sc, vb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(h, hipMemcpyAsync(c.sj, h->sj, vb, hipMemcpyDeviceToDevice, st));
+        for (int q = 0; q < 2; ++q) {
+            HIP_TRY(h, hipMemcpyAsync(c.seq[q], h->seq_d + seqs[q], sizeof(SeqDev),
+                                      hipMemcpyDeviceToDevice, st));
+            HIP_TRY(h, hipMemcpyAsync(c.hist[q], h->hist[seqs[q]], w.hist_bytes,
+                                      hipMemcpyDeviceToDevice, st));
+        }
+    } else {
+        HIP_TRY(h, hipMemcpyAsync(h->sc, c.sc, vb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(h, hipMemcpyAsync(h->sj, c.sj, vb, hipMemcpyDeviceToDevice, st));
+        for (int q = 0; q < 2; ++q) {
+            HIP_TRY(h, hipMemcpyAsync(h->seq_d + seqs[q], c.seq[q], sizeof(SeqDev),
+                                      hipMemcpyDeviceToDevice, st));
+            HIP_TRY(h, hipMemcpyAsync(h->hist[seqs[q]], c.hist[q], w.hist_bytes,
+                                      hipMemcpyDeviceToDevice, st));
+        }
+    }
+    return EC_OK;
+}
+
+extern "C" int32_t ec_adjoint_sizes(ec_handle h, int64_t n_steps, int32_t checkpoint_every,
+                                    int64_t *bytes)
+{
+    NEED_BOUND(h);
+    if (n_steps < 1 || checkpoint_every < 1 || !bytes)
+        return fail(h, EC_ERR_ARG, "need n_steps >= 1, checkpoint_every >= 1, bytes");
+    AdjWs w;
+    *bytes = adj_layout(h, n_steps, checkpoint_every, nullptr, &w);
+    return EC_OK;
+}
+
+static int32_t adj_args(ec_problem *h, int64_t n_steps, double dt, int32_t every,
+                        const ec_step_opts *opts, void *ws, int64_t bytes, double *A, AdjWs *w)
+{
+    int32_t rc = check_step_args(h, dt, A ? A : h->ac, opts);
+    if (rc) return rc;
+    if (!h->has_cond) return fail(h, EC_ERR_ARG, "the adjoint needs a conductor");
+    if (n_steps < 1 || every < 1) return fail(h, EC_ERR_ARG, "need n_steps >= 1, every >= 1");
+    if (!ws || ((uintptr_t)ws % kAlign) != 0)
+        return fail(h, EC_ERR_ARG, "adjoint workspace must be 256-byte aligned");
+    const int64_t need = adj_layout(h, n_steps, every, (char *)ws, w);
+    if (bytes < need) return fail(h, EC_ERR_ARG, "adjoint workspace too small (%lld < %lld)",
+                                  (long long)bytes, (long long)need);
+    return EC_OK;
+}
+
+extern "C" int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt,
+                                      int32_t checkpoint_every, const ec_step_opts *opts,
+                                      void *adj_ws, int64_t adj_bytes, double *A, double *loss)
+{
+    NEED_BOUND(h);
+    AdjWs w;
+    int32_t rc = adj_args(h, n_steps, dt, checkpoint_every, opts, adj_ws, adj_bytes, A, &w);
+    if (rc) return rc;
+    hipStream_t st = h->st;
+    const int nc = h->nc;
+    rc = set_state_impl(h, A, &opts->solve);           // a^0 from A; s_c, empty histories
+    if (rc) return rc;
+    adj_zero(w.acc, 4, st);
+    double *prev = w.seg, *cur = w.seg + std::max(nc, 1);
+    gather_c(h->cslot_d, nc, A, prev, st);
+    for (int64_t m = 1; m <= n_steps; ++m) {
+        if ((m - 1) % checkpoint_every == 0) {
+            rc = ckpt_copy(h, w, (m - 1) / checkpoint_every, prev, true);
+            if (rc) return rc;
+        }
+        rc = step_impl(h, m, dt, A, opts, nullptr);
+        if (rc) return rc;
+        gather_c(h->cslot_d, nc, A, cur, st);
+        const int nb = adj_loss(nc, cur, prev, h->minv_d, dt, w.part, st);
+        adj_accum(w.part, nb, 1.0, w.acc, st);
+        std::swap(prev, cur);
+    }
+    if (loss) HIP_TRY(h, hipMemcpyAsync(loss, w.acc, 8, hipMemcpyDeviceToDevice, st));
+    h->adj_ws = adj_ws;
+    h->adj_steps = n_steps;
+    h->adj_every = checkpoint_every;
+    h->adj_dt = dt;
+    return launch_check(h, "adjoint forward");
+}
+
+extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
+                                       int32_t checkpoint_every, const ec_step_opts *opts,
+                                       void *adj_ws, int64_t adj_bytes, int32_t mat_id,
+                                       double *grads)
+{
+    NEED_BOUND(h);
+    AdjWs w;
+    int32_t rc = adj_args(h, n_steps, dt, checkpoint_every, opts, adj_ws, adj_bytes, nullptr, &w);
+    if (rc) return rc;
+    if (h->adj_ws != adj_ws || h->adj_steps != n_steps || h->adj_every != checkpoint_every ||
+        h->adj_dt != dt)
+        return fail(h, EC_ERR_STATE, "ec_adjoint_forward with the same workspace, n_steps, "
+                                     "checkpoint_every and dt first");
+    if (mat_id < 1 || mat_id >= h->mats.n)
+        return fail(h, EC_ERR_ARG, "mat_id must be 1..%d", h->mats.n - 1);
+    if (!grads) return fail(h, EC_ERR_ARG, "grads is NULL");
+    hipStream_t st = h->st;
+    const int nc = h->nc, every = checkpoint_every;
+    const int64_t M = n_steps;
+    // dM_c/dsigma of the material: quarter dual faces of its cells per edge
+    std::vector<double> phi;
+    conductivities(h, &mat_id, &phi);
+    HIP_TRY(h, hipMemcpyAsync(w.phi, phi.data(), (size_t)nc * 8, hipMemcpyHostToDevice, st));
+    adj_zero(w.acc, 4, st);
+    adj_cell_init(w.cellv, h->ncell, h->mats.nu0, st);
+    fill(w.wpad, 0.0, h->npad, st);
+    fill(w.apad, 0.0, h->npad, st);
+    fill(w.badj, 0.0, h->npad, st);
+    fill(w.aseg, 0.0, h->npad, st);
+    fill(w.mu_b, 0.0, nc, st);
+    fill(w.dnext, 0.0, nc, st);
+    const int meth = opts->start_method;
+    if (meth == EC_SV_SPE || meth == EC_SV_POD) {
+        seq_ensure(h, EC_SEQ_ADJ, meth, opts->window, opts->pod_kmax, opts->pod_eps);
+        seq_eta_ensure(h, EC_SEQ_ADJ, meth, spe_eta(h, opts->solve.precision));
+    }
+    seq_reset(h->seq_d + EC_SEQ_ADJ, st);
+    double *mu_next = w.mu_b, *mu_cur = w.mu_a;
+    for (int64_t k = w.n_ckpt - 1; k >= 0; --k) {
+        const int64_t m0 = k * every, m1 = std::min<int64_t>(M, m0 + every);
+        // recompute the segment from its checkpoint
+        rc = ckpt_copy(h, w, k, nullptr, false);
+        if (rc) return rc;
+        const CkPtrs c = ckpt(h, w, k);
+        if (nc) HIP_TRY(h, hipMemcpyAsync(w.seg, c.ac, (size_t)nc * 8, hipMemcpyDeviceToDevice, st));
+        scatter_c(h->cslot_d, nc, w.seg, w.aseg, st);
+        for (int64_t m = m0 + 1; m <= m1; ++m) {
+            rc = step_impl(h, m, dt, w.aseg, opts, nullptr);
+            if (rc) return rc;
+            gather_c(h->cslot_d, nc, w.aseg, w.seg + (m - m0) * (int64_t)nc, st);
+        }
+        // adjoint steps m1 .. m0+1
+        for (int64_t m = m1; m > m0; --m) {
+            const double *am = w.seg + (m - m0) * (int64_t)nc;
+            const double *am1 = w.seg + (m - m0 - 1) * (int64_t)nc;
+            int nb;
+            if (m == M) {
+                nb = adj_mu(nc, am, am1, nullptr, w.dnext, h->minv_d, w.phi, nullptr, dt, 1,
+                            mu_cur, w.part, st);
+            } else {
+                // w = M_c^{-1} mu_{m+1}; cell pass at a^m (and the k1 term of step m+1)
+                adj_w(h->cslot_d, nc, mu_next, h->minv_d, w.wpad, st);
+                scatter_c(h->cslot_d, nc, am, w.apad, st);
+                const int nbc = adj_cell(h->g, h->mats_d, h->cmat_d, w.apad, w.wpad, w.cellv,
+                                         mat_id, h->bblo, h->bbhi, w.part, st);
+                adj_accum(w.part, nbc, -dt, w.acc + 2, st);
+                // S w = K_cn K_n^+ K_cn^T w through one solve of the adjoint sequence
+                spmv(h->g, w.wpad, w.badj, h->band_lo, h->band_hi, st);
+                rc = do_solve(h, EC_SEQ_ADJ, meth, opts->window, opts->pod_kmax, opts->pod_eps,
+                              w.badj, nullptr, w.sadj, &opts->solve, nullptr, true);
+                if (rc) return rc;
+                negate(w.sadj, w.upad, h->npad, st);
+                adj_w(h->cslot_d, nc, mu_next, h->minv_d, w.upad, st);
+                adj_edge(h->g, h->cslot_d, nc, w.cellv, w.upad, w.jt, st);
+                nb = adj_mu(nc, am, am1, mu_next, w.dnext, h->minv_d, w.phi, w.jt, dt, 0, mu_cur,
+                            w.part, st);
+            }
+            adj_accum(w.part, nb, 1.0, w.acc + 1, st);
+            std::swap(mu_cur, mu_next);
+        }
+    }
+    // k1 term of step 1: w_1 = M_c^{-1} mu_1 at a^0 (the first segment's start)
+    adj_w(h->cslot_d, nc, mu_next, h->minv_d, w.wpad, st);
+    scatter_c(h->cslot_d, nc, w.seg, w.apad, st);
+    const int nbc = adj_cell(h->g, h->mats_d, h->cmat_d, w.apad, w.wpad, w.cellv, mat_id, h->bblo,
+                             h->bbhi, w.part, st);
+    adj_accum(w.part, nbc, -dt, w.acc + 2, st);
+    HIP_TRY(h, hipMemcpyAsync(grads, w.acc + 1, 16, hipMemcpyDeviceToDevice, st));
+    return launch_check(h, "adjoint backward");
+}
+
 extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
                                          const ec_step_opts *opts, ec_solve_info *dev_info,
                                          void **graph_exec)

@@ -251,6 +251,24 @@ void refine_final(double *x, const Ctrl *ctrl, int64_t n, hipStream_t st);
 void refine_reset(Ctrl *ctrl, hipStream_t st);
 void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st);
 void negate(const double *x, double *y, int64_t n, hipStream_t st);
+
+// discrete adjoint of the time loop (ec_adjoint.hip); the *part launchers
+// return the number of block partials they wrote
+void adj_cell_init(double *cellv, int64_t ncell, double nu0, hipStream_t st);
+int adj_cell(const Geo &g, const Mats *mt, const uint8_t *cmat, const double *a, const double *w,
+             double *cellv, int mat, const int lo[3], const int hi[3], double *part,
+             hipStream_t st);
+void adj_edge(const Geo &g, const int *cslot, int nc, const double *cellv, const double *u,
+              double *out, hipStream_t st);
+int adj_mu(int nc, const double *a_m, const double *a_m1, const double *mu_next, double *d_next,
+           const double *minv, const double *phi, const double *jt, double dt, int terminal,
+           double *mu_out, double *part, hipStream_t st);
+void adj_w(const int *cslot, int nc, const double *mu, const double *minv, double *y,
+           hipStream_t st);
+int adj_loss(int nc, const double *a_new, const double *a_old, const double *minv, double dt,
+             double *part, hipStream_t st);
+void adj_accum(const double *part, int nb, double coef, double *acc, hipStream_t st);
+void adj_zero(double *acc, int n, hipStream_t st);
 void gather_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
 void scatter_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
 

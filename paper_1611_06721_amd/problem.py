@@ -189,6 +189,38 @@ class Problem:
             self._chk(self.lib.ec_cfl(self.h, _ptr(A), iters, rtol, C.byref(lam)))
         return lam.value
 
+    def set_material(self, mat_id, sigma, k1, k2, k3):
+        m = L.Material(float(sigma), float(k1), float(k2), float(k3))
+        with self._on_stream():
+            self._chk(self.lib.ec_set_material(self.h, int(mat_id), C.byref(m)))
+
+    def adjoint_workspace(self, n_steps, every):
+        b = C.c_int64()
+        self._chk(self.lib.ec_adjoint_sizes(self.h, int(n_steps), int(every), C.byref(b)))
+        ws = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+        return ws, (-ws.data_ptr()) % 256, b.value
+
+    def adjoint_forward(self, A, n_steps, dt, every, opts, ws):
+        """Joule loss of n_steps steps from A (device scalar); A ends at a^M."""
+        buf, off, nb = ws
+        loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        with self._on_stream():
+            self._chk(self.lib.ec_adjoint_forward(self.h, int(n_steps), float(dt), int(every),
+                                                  C.byref(opts), C.c_void_p(buf.data_ptr() + off),
+                                                  nb, _ptr(A), _ptr(loss)))
+        return loss
+
+    def adjoint_backward(self, n_steps, dt, every, opts, ws, mat_id=1):
+        """(dL/dsigma, dL/dk1) of material mat_id as a device tensor [2]."""
+        buf, off, nb = ws
+        g = torch.zeros(2, dtype=torch.float64, device=self.device)
+        with self._on_stream():
+            self._chk(self.lib.ec_adjoint_backward(self.h, int(n_steps), float(dt), int(every),
+                                                   C.byref(opts),
+                                                   C.c_void_p(buf.data_ptr() + off), nb,
+                                                   int(mat_id), _ptr(g)))
+        return g
+
     def graph_capture(self, A, dt, opts, info=None):
         g = C.c_void_p()
         with self._on_stream():
