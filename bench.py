@@ -140,6 +140,63 @@ def precision_c3(ec, torch, steps, warmup, rtol=1e-8, N=128):
     return out
 
 
+def adjoint_c5(ec, torch, steps=500, every=50, N=64, rtol=1e-8, check_steps=100):
+    """Hand-written adjoint on the 64^3 Brauer grid: forward steps with a
+    checkpoint every `every` steps (Joule loss), then the backward pass
+    (segment recompute + adjoint recursion, dL/dsigma and dL/dk1), timed with
+    events; the gradients of a `check_steps` run at rtol 1e-12 are compared
+    with central differences of the GPU loss."""
+    import synth
+    wl = synth.nonlinear(N)
+    G = ec.Problem(wl, window_cap=8)
+    dt = 0.5 * 2.0 / G.cfl(iters=40, rtol=1e-10)
+    opts = ec.step_opts(ec.SV_SPE, window=8, rtol=rtol)
+    ws = G.adjoint_workspace(steps, every)
+    s = G.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    G.counters_reset()
+    A = G.zeros()
+    ev[0].record(s)
+    loss = G.adjoint_forward(A, steps, dt, every, opts, ws)
+    ev[1].record(s)
+    c_fwd = G.counters()
+    g = G.adjoint_backward(steps, dt, every, opts, ws, 1)
+    ev[2].record(s)
+    ev[2].synchronize()
+    c_all = G.counters()
+    t_f, t_b = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    gr = g.cpu().numpy()
+    out = {"workload": f"nonlinear {N}^3, {steps} steps, checkpoint every {every}, SPE m=8, "
+                       f"rtol {rtol:g}",
+           "loss": float(loss.item()), "dL_dsigma": float(gr[0]), "dL_dk1": float(gr[1]),
+           "forward_steps_per_s": round(steps / (t_f * 1e-3), 2),
+           "backward_steps_per_s": round(steps / (t_b * 1e-3), 2),
+           "forward_iters_per_step": round((c_fwd["iters_src"] + c_fwd["iters_cpl"]) / steps, 3),
+           "adjoint_iters_per_step": round(c_all["iters_adj"] / steps, 3),
+           "workspace_MB": round(ws[2] / 2 ** 20, 1)}
+    del ws
+    # gradient check at rtol 1e-12 on the first check_steps steps
+    m = wl.materials[0]
+    o12 = ec.step_opts(ec.SV_SPE, window=8, rtol=1e-12)
+    wsc = G.adjoint_workspace(check_steps, every)
+    G.set_material(1, m.sigma, m.k1, m.k2, m.k3)
+    G.adjoint_forward(G.zeros(), check_steps, dt, every, o12, wsc)
+    gc = G.adjoint_backward(check_steps, dt, every, o12, wsc, 1).cpu().numpy()
+
+    def L(sigma, k1):
+        G.set_material(1, sigma, k1, m.k2, m.k3)
+        return float(G.adjoint_forward(G.zeros(), check_steps, dt, every, o12, wsc).item())
+    h = 1e-4
+    fd_s = (L(m.sigma * (1 + h), m.k1) - L(m.sigma * (1 - h), m.k1)) / (2 * h * m.sigma)
+    fd_k = (L(m.sigma, m.k1 * (1 + h)) - L(m.sigma, m.k1 * (1 - h))) / (2 * h * m.k1)
+    out["fd_check"] = {"steps": check_steps, "rtol": 1e-12, "h": h,
+                       "rel_err_dsigma": float(abs(gc[0] - fd_s) / abs(fd_s)),
+                       "rel_err_dk1": float(abs(gc[1] - fd_k) / abs(fd_k))}
+    del G, wsc
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_cg_iteration(ec, torch, G, reps=400):
     """Average duration of one PCG iteration kernel (FP64, every iteration
     active): solves that run exactly 100 and 100 + reps iterations, timed with
@@ -223,6 +280,7 @@ def main():
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 FP64 / FP32-refined runs")
     ap.add_argument("--c3-steps", type=int, default=200)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 64^3 adjoint runs")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the dominant-kernel timing and a 512 MiB device copy "
                          "(the reference for the HBM byte counters)")
@@ -296,6 +354,12 @@ def main():
     if not args.no_c3:
         c3 = precision_c3(ec, torch, args.c3_steps, args.warmup)
 
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_c5(ec, torch)
+        log(f"[bench] adjoint 64^3: forward {adj['forward_steps_per_s']} steps/s, backward "
+            f"{adj['backward_steps_per_s']} steps/s, fd check {adj['fd_check']}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_steps, dt)
@@ -327,6 +391,7 @@ def main():
         "roofline": roofline,
         "probe": extra,
         "precision_128": c3,
+        "adjoint_64": adj,
         "cpu_baseline": cpu,
     }
     if "zero" in results and head != "zero":

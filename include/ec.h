@@ -273,7 +273,8 @@ int32_t ec_set_material(ec_handle h, int32_t mat_id, const ec_material *m);
  * grads (device double[2]) = {dL/dsigma, dL/dk1} of material mat_id.  It
  * leaves the stepping state of a recomputed segment behind: call
  * ec_set_state before stepping again.  EC_ERR_ARG for bad sizes, ids or a
- * workspace below ec_adjoint_sizes. */
+ * workspace below ec_adjoint_sizes; EC_ERR_NONFINITE when the loss or the
+ * gradients are not finite (a diverging run).  Both synchronise. */
 int32_t ec_adjoint_sizes(ec_handle h, int64_t n_steps, int32_t checkpoint_every, int64_t *bytes);
 int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt, int32_t checkpoint_every,
                            const ec_step_opts *opts, void *adj_ws, int64_t adj_bytes, double *A,

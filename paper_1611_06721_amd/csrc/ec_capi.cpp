@@ -1299,6 +1299,12 @@ extern "C" int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt,
         std::swap(prev, cur);
     }
     if (loss) HIP_TRY(h, hipMemcpyAsync(loss, w.acc, 8, hipMemcpyDeviceToDevice, st));
+    double chk = 0.0;
+    HIP_TRY(h, hipMemcpyAsync(&chk, w.acc, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    if (!std::isfinite(chk))
+        return fail(h, EC_ERR_NONFINITE, "adjoint forward: the run diverged (loss %g); dt above "
+                                         "the stability bound of eq. (8)?", chk);
     h->adj_ws = adj_ws;
     h->adj_steps = n_steps;
     h->adj_every = checkpoint_every;
@@ -1394,6 +1400,11 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
                              h->bbhi, w.part, st);
     adj_accum(w.part, nbc, -dt, w.acc + 2, st);
     HIP_TRY(h, hipMemcpyAsync(grads, w.acc + 1, 16, hipMemcpyDeviceToDevice, st));
+    double chk[2] = {0.0, 0.0};
+    HIP_TRY(h, hipMemcpyAsync(chk, w.acc + 1, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    if (!std::isfinite(chk[0]) || !std::isfinite(chk[1]))
+        return fail(h, EC_ERR_NONFINITE, "adjoint backward: non-finite gradient");
     return launch_check(h, "adjoint backward");
 }
 

@@ -122,3 +122,27 @@ def test_eddy_loss_autograd(ec, oracle_mod):
     k1.grad = None
     (3.0 * ec.eddy_loss(sigma, k1, G, dt, M, every=4, opts=opts)).backward()
     assert float(sigma.grad) == pytest.approx(3.0 * gs_o, rel=1e-8)
+
+
+def test_adjoint_full_size_central_difference(ec, oracle_mod):
+    """64^3 grid (the adjoint workload's shape), 30 SPE steps at rtol 1e-12:
+    the adjoint gradients against central differences of the GPU loss."""
+    wl = synth.nonlinear(64, ramp_steps=30, J0=6.0e6)
+    G = ec.Problem(wl, window_cap=8)
+    dt = 0.5 * 2 / G.cfl(iters=40, rtol=1e-10)
+    M, every = 30, 10
+    opts = ec.step_opts(ec.SV_SPE, window=8, rtol=1e-12)
+    loss, g, _ = gpu_grads(ec, G, dt, M, every, opts)
+    m = wl.materials[0]
+    ws = G.adjoint_workspace(M, every)
+
+    def L(sigma, k1):
+        G.set_material(1, sigma, k1, m.k2, m.k3)
+        return float(G.adjoint_forward(G.zeros(), M, dt, every, opts, ws).item())
+    # k1 moves the loss little in 30 steps: a step of 1e-4 keeps the
+    # difference well above the noise of rtol-1e-12 solves (truncation ~h^2)
+    h = 1e-4
+    fd_s = (L(m.sigma * (1 + h), m.k1) - L(m.sigma * (1 - h), m.k1)) / (2 * h * m.sigma)
+    fd_k = (L(m.sigma, m.k1 * (1 + h)) - L(m.sigma, m.k1 * (1 - h))) / (2 * h * m.k1)
+    assert g[0] == pytest.approx(fd_s, rel=5e-5)
+    assert g[1] == pytest.approx(fd_k, rel=5e-5)
