@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef struct ec_problem *ec_handle;
+typedef struct ec_batch_s *ec_batch;
 
 enum {
     EC_OK = 0,
@@ -282,6 +283,47 @@ int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt, int32_t chec
 int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt, int32_t checkpoint_every,
                             const ec_step_opts *opts, void *adj_ws, int64_t adj_bytes,
                             int32_t mat_id, double *grads);
+
+/* Batches of independent problems (uneven grids, materials and dt, e.g. the
+ * samples of a multi-query study) stepped together on one stream: every
+ * PCG iteration of all instances' source (or coupling) solves is one
+ * launch, each instance on its own slice of the grid with the arithmetic of
+ * a single-instance solve (a batched instance equals the same problem
+ * stepped alone, bitwise); start vectors, the conducting update and the
+ * histories run as each instance's kernels.  FP64 solves only.
+ *
+ * ec_batch_sizes / ec_batch_create: n bound handles (all bound to the same
+ * stream) and a caller-owned device workspace of ec_batch_sizes bytes
+ * (256-byte aligned).  The batch borrows the handles (destroy it first).
+ * ec_batch_step / ec_batch_run: dt[i] (host array) and A[i] (host array of
+ * device state pointers) per instance; m < 0 (step) or m0 < 0 (run) takes
+ * each instance's step index from its device counter.  Per-instance
+ * counters (ec_counters) record the solves.  Eager calls synchronise once
+ * per handful of iterations to stop when every solve has finished.
+ * ec_batch_graph_capture: one step of every instance as one HIP graph
+ * (device step counters; opts->graph_iters = batched iterations per solve,
+ * 0 = solve.maxit up to 4096; a solve that needs more reports
+ * EC_ERR_NOT_CONVERGED in its instance's worst status); launch with
+ * ec_graph_launch.
+ * ec_batch_set_tiles / ec_batch_autotune: the tiles of 256 nodes each block
+ * of a batched iteration sweeps (1..64).  The autotuner times 1, 2, 4 and 8
+ * on the batch itself and keeps the fastest; with cache_path it first looks
+ * for a pick recorded for this device and batch shape and appends new picks
+ * (one text line each), so a cached batch always gets the same config.
+ * Errors: EC_ERR_ARG / EC_ERR_STATE; the message is ec_last_error(NULL). */
+int32_t ec_batch_sizes(int32_t n, const ec_handle *handles, int64_t *bytes);
+int32_t ec_batch_create(int32_t n, const ec_handle *handles, void *workspace, int64_t bytes,
+                        ec_batch *out);
+int32_t ec_batch_destroy(ec_batch b);
+int32_t ec_batch_step(ec_batch b, int64_t m, const double *dt, double *const *A,
+                      const ec_step_opts *opts);
+int32_t ec_batch_run(ec_batch b, int64_t m0, int64_t nsteps, const double *dt, double *const *A,
+                     const ec_step_opts *opts);
+int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *const *A,
+                               const ec_step_opts *opts, void **graph_exec);
+int32_t ec_batch_set_tiles(ec_batch b, int32_t tiles_per_block);
+int32_t ec_batch_autotune(ec_batch b, const char *cache_path, int32_t *tiles_per_block,
+                          double *us_per_iter);
 
 /* HIP graph of one step (device step counter, fixed dt and opts) captured on
  * the bound stream; launch replays it on `hip_stream`. */

@@ -14,7 +14,8 @@ from ._lib import (EC_ERR_ARG, EC_ERR_BREAKDOWN, EC_ERR_CFL, EC_ERR_HIP,  # noqa
 
 def __getattr__(name):
     # torch-dependent pieces load lazily
-    if name in ("Problem", "Graph", "solve_opts", "step_opts", "info_array", "INFO_BYTES"):
+    if name in ("Problem", "Graph", "Batch", "solve_opts", "step_opts", "info_array",
+                "INFO_BYTES"):
         from . import problem
         return getattr(problem, name)
     if name in ("EddyLoss", "eddy_loss"):

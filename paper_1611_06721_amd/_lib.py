@@ -96,6 +96,18 @@ SIGNATURES = {
                                        _P, C.c_int64, _P, _P]),
     "ec_adjoint_backward": (C.c_int32, [_H, C.c_int64, C.c_double, C.c_int32,
                                         C.POINTER(StepOpts), _P, C.c_int64, C.c_int32, _P]),
+    "ec_batch_sizes": (C.c_int32, [C.c_int32, C.POINTER(_H), C.POINTER(C.c_int64)]),
+    "ec_batch_create": (C.c_int32, [C.c_int32, C.POINTER(_H), _P, C.c_int64, C.POINTER(_P)]),
+    "ec_batch_destroy": (C.c_int32, [_P]),
+    "ec_batch_step": (C.c_int32, [_P, C.c_int64, C.POINTER(C.c_double), C.POINTER(_P),
+                                  C.POINTER(StepOpts)]),
+    "ec_batch_run": (C.c_int32, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_double),
+                                 C.POINTER(_P), C.POINTER(StepOpts)]),
+    "ec_batch_graph_capture": (C.c_int32, [_P, C.POINTER(C.c_double), C.POINTER(_P),
+                                           C.POINTER(StepOpts), C.POINTER(C.c_void_p)]),
+    "ec_batch_set_tiles": (C.c_int32, [_P, C.c_int32]),
+    "ec_batch_autotune": (C.c_int32, [_P, C.c_char_p, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_double)]),
     "ec_graph_capture_step": (C.c_int32, [_H, C.c_double, _P, C.POINTER(StepOpts), _P,
                                           C.POINTER(C.c_void_p)]),
     "ec_graph_launch": (C.c_int32, [_P, _P]),

@@ -675,8 +675,8 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
     return launch_check(h, "cg");
 }
 
-static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const double *bscale,
-                        double *x, const ec_solve_opts *o, ec_solve_info *info)
+static CgArgs<double> cg64_args(ec_problem *h, int seq, const double *b, const double *bscale,
+                                double *x, const ec_solve_opts *o, ec_solve_info *info)
 {
     CgArgs<double> a{};
     a.g = h->g;
@@ -698,6 +698,11 @@ static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const
     a.tiles = h->tiles;
     a.blocks = h->cg_blocks;
     a.bar = h->bar;
+    return a;
+}
+
+static void cg64_init(ec_problem *h, CgArgs<double> a, int mode)
+{
     if (mode == START_X) {
         a.mode = START_X;
         cg_init<double>(a, h->st);
@@ -707,6 +712,13 @@ static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const
         a.mode = mode;
         cg_init<double>(a, h->st);
     }
+}
+
+static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const double *bscale,
+                        double *x, const ec_solve_opts *o, ec_solve_info *info)
+{
+    CgArgs<double> a = cg64_args(h, seq, b, bscale, x, o, info);
+    cg64_init(h, a, mode);
     int issued = 0;
     int32_t rc = cg_iterate<double>(h, a, seq, true, &issued);
     if (rc) return rc;
@@ -767,29 +779,38 @@ static int32_t run_refined(ec_problem *h, int seq, const double *b, const double
     return launch_check(h, "refined solve");
 }
 
-static int32_t do_solve(ec_problem *h, int seq, int method, int window, int kmax, double eps,
-                        const double *b, const double *bscale, double *x, const ec_solve_opts *o,
-                        ec_solve_info *info, bool push)
+// start vector of a solve (eqs. 10, 14 for SPE / POD) and the PCG start mode
+static int32_t solve_prepare(ec_problem *h, int seq, int method, int window, int kmax,
+                             double eps, const double *b, const double *bscale, double *x,
+                             const ec_solve_opts *o, ec_solve_info *info, int *mode)
 {
     if (o->precision != EC_PREC_FP64 && o->precision != EC_PREC_FP32_REFINED)
         return fail(h, EC_ERR_ARG, "unknown precision %d", o->precision);
     if (!(o->rtol > 0) || o->maxit < 0) return fail(h, EC_ERR_ARG, "need rtol > 0, maxit >= 0");
-    int mode;
     if (method == EC_SV_ZERO) {
-        mode = START_ZERO;
+        *mode = START_ZERO;
     } else if (method == EC_SV_PREV) {
-        mode = START_X;
+        *mode = START_X;
     } else if (method == EC_SV_SPE || method == EC_SV_POD) {
         if (window < 1 || window > h->cap)
             return fail(h, EC_ERR_ARG, "window must be 1..%d (the bound window_cap)", h->cap);
         seq_ensure(h, seq, method, window, kmax, eps);
         seq_eta_ensure(h, seq, method, spe_eta(h, o->precision));
         seq_start(h, seq, method, b, bscale, x, info);
-        mode = START_DEV;
+        *mode = START_DEV;
     } else {
         return fail(h, EC_ERR_ARG, "unknown start method %d", method);
     }
-    int32_t rc;
+    return EC_OK;
+}
+
+static int32_t do_solve(ec_problem *h, int seq, int method, int window, int kmax, double eps,
+                        const double *b, const double *bscale, double *x, const ec_solve_opts *o,
+                        ec_solve_info *info, bool push)
+{
+    int mode = 0;
+    int32_t rc = solve_prepare(h, seq, method, window, kmax, eps, b, bscale, x, o, info, &mode);
+    if (rc) return rc;
     if (o->precision == EC_PREC_FP64) {
         rc = run_cg64(h, seq, mode, b, bscale, x, o, info);
     } else {
@@ -1406,6 +1427,393 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
     if (!std::isfinite(chk[0]) || !std::isfinite(chk[1]))
         return fail(h, EC_ERR_NONFINITE, "adjoint backward: non-finite gradient");
     return launch_check(h, "adjoint backward");
+}
+
+
+// ---------------------------------------------------------------- batch
+// Independent problems of uneven size (their own grid, materials and dt)
+// advanced together on one stream.  Start vectors, the nonlinear update and
+// the histories run as each problem's own kernels; the PCG iterations of all
+// solves run in one launch per iteration (k_cg_iter_batch), each instance on
+// its own slice of the grid with exactly the single-instance arithmetic.
+struct ec_batch_s {
+    std::vector<ec_problem *> inst;
+    hipStream_t st = nullptr;
+    CgArgs<double> *tab_d[2] = {};                 // per sequence: SRC, CPL
+    std::vector<CgArgs<double>> tab[2];
+    int *inst_d = nullptr, *off_d = nullptr, *flag_d = nullptr;
+    int total_blocks = 0, max_blocks = 0;
+    int tiles_per_block = 1;
+};
+
+static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_batch_s *b)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        const int64_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return base ? base + o : nullptr;
+    };
+    const int64_t n = (int64_t)hs.size();
+    int64_t maxb = 0;
+    for (ec_problem *h : hs) maxb += std::min<int64_t>(align_up(h->tiles, 8), kMaxBlocks);
+    CgArgs<double> *t0 = (CgArgs<double> *)take(n * sizeof(CgArgs<double>));
+    CgArgs<double> *t1 = (CgArgs<double> *)take(n * sizeof(CgArgs<double>));
+    int *im = (int *)take(maxb * 4);
+    int *of = (int *)take(n * 4);
+    int *fl = (int *)take(64);
+    if (b) {
+        b->tab_d[0] = t0;
+        b->tab_d[1] = t1;
+        b->inst_d = im;
+        b->off_d = of;
+        b->flag_d = fl;
+        b->max_blocks = (int)maxb;
+    }
+    return off;
+}
+
+// PCG grid of each instance for a tiles-per-block factor, and the block map
+static int32_t batch_apply_tiles(ec_batch_s *b, int f)
+{
+    std::vector<int> im, of;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        ec_problem *h = b->inst[i];
+        const int64_t nb = std::max<int64_t>(8, std::min<int64_t>(align_up((h->tiles + f - 1) / f, 8),
+                                                                  kMaxBlocks));
+        h->cg_blocks = (int)nb;
+        of.push_back((int)im.size());
+        for (int64_t q = 0; q < nb; ++q) im.push_back((int)i);
+    }
+    b->total_blocks = (int)im.size();
+    b->tiles_per_block = f;
+    ec_problem *h0 = b->inst[0];
+    HIP_TRY(h0, hipMemcpyAsync(b->inst_d, im.data(), im.size() * 4, hipMemcpyHostToDevice, b->st));
+    HIP_TRY(h0, hipMemcpyAsync(b->off_d, of.data(), of.size() * 4, hipMemcpyHostToDevice, b->st));
+    HIP_TRY(h0, hipStreamSynchronize(b->st));
+    return EC_OK;
+}
+
+// per-instance PCG arguments of the source / coupling solves (device tables)
+static int32_t batch_tables(ec_batch_s *b, const ec_solve_opts *o)
+{
+    for (int s = 0; s < 2; ++s) {
+        b->tab[s].clear();
+        for (ec_problem *h : b->inst) {
+            if (s == 0) b->tab[s].push_back(cg64_args(h, EC_SEQ_SRC, h->xs_d, &h->ctrl_d->scale,
+                                                      h->sj, o, nullptr));
+            else b->tab[s].push_back(cg64_args(h, EC_SEQ_CPL, h->bcpl, nullptr, h->sc, o, nullptr));
+        }
+        ec_problem *h0 = b->inst[0];
+        HIP_TRY(h0, hipMemcpyAsync(b->tab_d[s], b->tab[s].data(),
+                                   b->tab[s].size() * sizeof(CgArgs<double>),
+                                   hipMemcpyHostToDevice, b->st));
+    }
+    HIP_TRY(b->inst[0], hipStreamSynchronize(b->st));
+    return EC_OK;
+}
+
+static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
+{
+    const int seq = s == 0 ? EC_SEQ_SRC : EC_SEQ_CPL;
+    const int meth = o->start_method;
+    const int n = (int)b->inst.size();
+    for (int i = 0; i < n; ++i) {
+        ec_problem *h = b->inst[i];
+        const CgArgs<double> &a = b->tab[s][i];
+        int mode = 0;
+        int32_t rc = solve_prepare(h, seq, meth, o->window, o->pod_kmax, o->pod_eps, a.b, a.bscale,
+                                   a.x, &o->solve, nullptr, &mode);
+        if (rc) return rc;
+        cg64_init(h, a, mode);
+    }
+    const int maxit = o->solve.maxit;
+    int issued = 0;
+    ec_problem *h0 = b->inst[0];
+    if (capturing(h0)) {
+        int budget = std::min(maxit, kGraphMaxIters);
+        if (o->graph_iters[s] > 0) budget = std::min(budget, o->graph_iters[s]);
+        for (int it = 0; it < budget; ++it)
+            cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, it, b->st);
+        issued = budget;
+    } else {
+        int chunk = 8;
+        while (issued < maxit) {
+            const int c = std::min(chunk, maxit - issued);
+            for (int j = 0; j < c; ++j)
+                cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, issued + j, b->st);
+            issued += c;
+            batch_done(b->tab_d[s], n, issued, b->flag_d, b->st);
+            HIP_TRY(h0, hipMemcpyAsync(h0->pin + 20, b->flag_d, 4, hipMemcpyDeviceToHost, b->st));
+            HIP_TRY(h0, hipStreamSynchronize(b->st));
+            if (h0->pin[20]) break;
+            chunk = std::min(2 * chunk, 256);
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        ec_problem *h = b->inst[i];
+        cg_fin<double>(b->tab[s][i], issued, b->st);
+        if (meth == EC_SV_SPE || meth == EC_SV_POD) seq_push(h, seq, meth, b->tab[s][i].x);
+    }
+    return launch_check(h0, "batch solve");
+}
+
+static int32_t batch_step_impl(ec_batch_s *b, int64_t m, const double *dt, double *const *A,
+                               const ec_step_opts *o)
+{
+    const int n = (int)b->inst.size();
+    for (int i = 0; i < n; ++i) {
+        ec_problem *h = b->inst[i];
+        step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt[i], b->st);
+    }
+    int32_t rc = batch_solve(b, 0, o);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        ec_problem *h = b->inst[i];
+        UpdArgs u{};
+        u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d;
+        u.minv = h->minv_d; u.nc = h->nc; u.A = A[i]; u.sj = h->sj; u.sc = h->sc; u.out = h->ac;
+        u.dt = dt[i]; u.apply = 0; u.ctrl = h->ctrl_d;
+        update_c(u, b->st);
+        if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, b->st);
+    }
+    rc = batch_solve(b, 1, o);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        ec_problem *h = b->inst[i];
+        finish_state(h->g, A[i], h->ac, h->sj, h->sc, h->ctrl_d, 1, b->st);
+    }
+    return launch_check(b->inst[0], "batch step");
+}
+
+static int32_t batch_check(ec_batch_s *b, const double *dt, double *const *A,
+                           const ec_step_opts *o)
+{
+    if (!b) return fail(nullptr, EC_ERR_ARG, "batch is NULL");
+    if (!dt || !A || !o) return fail(nullptr, EC_ERR_ARG, "dt, A and opts are required");
+    if (o->solve.precision != EC_PREC_FP64)
+        return fail(nullptr, EC_ERR_ARG, "batched steps run FP64 solves");
+    if (o->graph_iters[0] < 0 || o->graph_iters[1] < 0)
+        return fail(nullptr, EC_ERR_ARG, "graph_iters must be >= 0");
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        int32_t rc = check_step_args(b->inst[i], dt[i], A[i], o);
+        if (rc) return fail(nullptr, rc, "instance %zu: %s", i, b->inst[i]->err.c_str());
+    }
+    return EC_OK;
+}
+
+extern "C" int32_t ec_batch_sizes(int32_t n, const ec_handle *handles, int64_t *bytes)
+{
+    if (n < 1 || !handles || !bytes) return fail(nullptr, EC_ERR_ARG, "need n >= 1, handles, bytes");
+    std::vector<ec_problem *> hs(handles, handles + n);
+    for (ec_problem *h : hs)
+        if (!h || !h->bound) return fail(nullptr, EC_ERR_STATE, "every handle must be bound");
+    *bytes = batch_layout(hs, nullptr, nullptr);
+    return EC_OK;
+}
+
+extern "C" int32_t ec_batch_create(int32_t n, const ec_handle *handles, void *workspace,
+                                   int64_t bytes, ec_batch *out)
+{
+    if (!out) return fail(nullptr, EC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int64_t need = 0;
+    int32_t rc = ec_batch_sizes(n, handles, &need);
+    if (rc) return rc;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || bytes < need)
+        return fail(nullptr, EC_ERR_ARG, "batch workspace: 256-byte aligned, >= %lld bytes",
+                    (long long)need);
+    std::vector<ec_problem *> hs(handles, handles + n);
+    for (ec_problem *h : hs)
+        if (h->st != hs[0]->st)
+            return fail(nullptr, EC_ERR_ARG, "every handle must be bound to the same stream");
+    ec_batch_s *b = new ec_batch_s();
+    b->inst = hs;
+    b->st = hs[0]->st;
+    batch_layout(hs, (char *)workspace, b);
+    rc = batch_apply_tiles(b, 1);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_batch_destroy(ec_batch b)
+{
+    delete b;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_batch_set_tiles(ec_batch b, int32_t tiles_per_block)
+{
+    if (!b || tiles_per_block < 1 || tiles_per_block > 64)
+        return fail(nullptr, EC_ERR_ARG, "tiles_per_block must be 1..64");
+    return batch_apply_tiles(b, tiles_per_block);
+}
+
+extern "C" int32_t ec_batch_step(ec_batch b, int64_t m, const double *dt, double *const *A,
+                                 const ec_step_opts *opts)
+{
+    int32_t rc = batch_check(b, dt, A, opts);
+    if (rc) return rc;
+    rc = batch_tables(b, &opts->solve);
+    if (rc) return rc;
+    return batch_step_impl(b, m, dt, A, opts);
+}
+
+extern "C" int32_t ec_batch_run(ec_batch b, int64_t m0, int64_t nsteps, const double *dt,
+                                double *const *A, const ec_step_opts *opts)
+{
+    int32_t rc = batch_check(b, dt, A, opts);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(nullptr, EC_ERR_ARG, "nsteps must be >= 0");
+    rc = batch_tables(b, &opts->solve);
+    if (rc) return rc;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        rc = batch_step_impl(b, m0 < 0 ? -1 : m0 + 1 + s, dt, A, opts);
+        if (rc) return rc;
+    }
+    return EC_OK;
+}
+
+extern "C" int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *const *A,
+                                          const ec_step_opts *opts, void **graph_exec)
+{
+    int32_t rc = batch_check(b, dt, A, opts);
+    if (rc) return rc;
+    if (!graph_exec) return fail(nullptr, EC_ERR_ARG, "graph_exec is NULL");
+    for (ec_problem *h : b->inst)
+        for (int s : {EC_SEQ_SRC, EC_SEQ_CPL}) {
+            seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
+            seq_eta_ensure(h, s, opts->start_method, spe_eta(h, opts->solve.precision));
+        }
+    rc = batch_tables(b, &opts->solve);
+    if (rc) return rc;
+    ec_problem *h0 = b->inst[0];
+    hipGraph_t graph = nullptr;
+    HIP_TRY(h0, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    rc = batch_step_impl(b, -1, dt, A, opts);
+    hipError_t e = hipStreamEndCapture(b->st, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+    *graph_exec = (void *)ex;
+    return EC_OK;
+}
+
+// Average duration of one batched PCG iteration (every instance active) for
+// the current grids: zero-start solves of the sources into scratch vectors.
+static int32_t batch_time_iteration(ec_batch_s *b, double *us)
+{
+    ec_solve_opts o{};
+    o.rtol = 1e-300;
+    o.maxit = 1 << 30;
+    std::vector<CgArgs<double>> t;
+    for (ec_problem *h : b->inst) {
+        CgArgs<double> a = cg64_args(h, EC_SEQ_USER, h->xs_d, &h->ctrl_d->one, h->t4, &o, nullptr);
+        a.ctrl = nullptr;
+        t.push_back(a);
+        cg64_init(h, a, START_ZERO);
+    }
+    ec_problem *h0 = b->inst[0];
+    HIP_TRY(h0, hipMemcpyAsync(b->tab_d[0], t.data(), t.size() * sizeof(CgArgs<double>),
+                               hipMemcpyHostToDevice, b->st));
+    const int warm = 4, reps = 40;
+    for (int it = 0; it < warm; ++it)
+        cg_iter_batch(b->tab_d[0], b->inst_d, b->off_d, b->total_blocks, it, b->st);
+    hipEvent_t e0, e1;
+    HIP_TRY(h0, hipEventCreate(&e0));
+    HIP_TRY(h0, hipEventCreate(&e1));
+    HIP_TRY(h0, hipEventRecord(e0, b->st));
+    for (int it = warm; it < warm + reps; ++it)
+        cg_iter_batch(b->tab_d[0], b->inst_d, b->off_d, b->total_blocks, it, b->st);
+    HIP_TRY(h0, hipEventRecord(e1, b->st));
+    HIP_TRY(h0, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(h0, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us = 1e3 * ms / reps;
+    return launch_check(h0, "batch timing");
+}
+
+static std::string batch_signature(const ec_batch_s *b)
+{
+    std::string sig;
+    hipDeviceProp_t prop{};
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        sig += prop.gcnArchName;
+    sig += ":n" + std::to_string(b->inst.size());
+    for (const ec_problem *h : b->inst)
+        sig += ":" + std::to_string(h->g.nx) + "x" + std::to_string(h->g.ny) + "x" +
+               std::to_string(h->g.nz);
+    return sig;
+}
+
+extern "C" int32_t ec_batch_autotune(ec_batch b, const char *cache_path, int32_t *tiles_per_block,
+                                     double *us_per_iter)
+{
+    if (!b) return fail(nullptr, EC_ERR_ARG, "batch is NULL");
+    const std::string sig = batch_signature(b);
+    // a cached pick for this device and batch shape
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[8192];
+            int best_f = 0;
+            double best_us = 0.0;
+            while (std::fgets(line, sizeof line, f)) {
+                char key[8000];
+                int ff = 0;
+                double uu = 0.0;
+                if (std::sscanf(line, "ec-batch-tiles %7999s %d %lf", key, &ff, &uu) == 3 &&
+                    sig == key && ff >= 1 && ff <= 64) {
+                    best_f = ff;
+                    best_us = uu;
+                }
+            }
+            std::fclose(f);
+            if (best_f) {
+                int32_t rc = batch_apply_tiles(b, best_f);
+                if (rc) return rc;
+                if (tiles_per_block) *tiles_per_block = best_f;
+                if (us_per_iter) *us_per_iter = best_us;
+                return EC_OK;
+            }
+        }
+    }
+    int best_f = 1;
+    double best_us = 1e300;
+    for (int f : {1, 2, 4, 8}) {
+        int32_t rc = batch_apply_tiles(b, f);
+        if (rc) return rc;
+        double us = 0.0;
+        rc = batch_time_iteration(b, &us);
+        if (rc) return rc;
+        if (us < best_us) {
+            best_us = us;
+            best_f = f;
+        }
+    }
+    int32_t rc = batch_apply_tiles(b, best_f);
+    if (rc) return rc;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "ec-batch-tiles %s %d %.4f\n", sig.c_str(), best_f, best_us);
+            std::fclose(f);
+        }
+    }
+    if (tiles_per_block) *tiles_per_block = best_f;
+    if (us_per_iter) *us_per_iter = best_us;
+    return EC_OK;
 }
 
 extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,

@@ -126,8 +126,24 @@ __device__ __forceinline__ void curlcurl_node(const Geo &g, int64_t n, LD ld, T 
     qz = wy * (Fy - Fy_im) - wx * (Fx - Fx_jm);
 }
 
-// Tile loop of a node kernel: blocks b = 8*loc + xcd sweep the tiles of
-// XCD slab xcd (contiguous k-planes stay in that XCD's L2).  nb % 8 == 0.
+// Tile loop of a node kernel run by block bid of nb (nb % 8 == 0): blocks
+// bid = 8*loc + xcd sweep the tiles of XCD slab xcd (contiguous k-planes stay
+// in that XCD's L2; a launch places block b on XCD b % 8, so a grid slice
+// starting at a multiple of 8 keeps the mapping).
+template <typename F>
+__device__ __forceinline__ void for_tiles_b(int tiles, int64_t S, int bid, int nb, F fn)
+{
+    const int xcd = bid & 7, loc = bid >> 3, nloc = nb >> 3;
+    const int tpx = (tiles + 7) >> 3;
+    for (int t = loc; t < tpx; t += nloc) {
+        const int tile = xcd * tpx + t;
+        if (tile >= tiles) break;
+        const int64_t n = (int64_t)tile * kTile + threadIdx.x;
+        if (n < S) fn(n);
+    }
+}
+
+// the same over the whole launch
 template <typename F>
 __device__ __forceinline__ void for_tiles(int tiles, int64_t S, F fn)
 {

@@ -153,6 +153,11 @@ template <typename T>
 void cg_iter(const CgArgs<T> &a, int i, hipStream_t st);
 template <typename T>
 void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st);
+// batched iteration: all solves of a batch, one launch (block map inst/off)
+void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
+                   int it, hipStream_t st);
+// *flag (device int) = 1 if every solve of tab[0..n) finished before iteration it
+void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t st);
 // blocks of the cooperative tail (one per CU, a multiple of 8; 0 on failure)
 template <typename T>
 int cg_tail_blocks();

@@ -300,7 +300,7 @@ __device__ __forceinline__ CgCtl cg_state(const CgCtl &prev, const double (&t)[4
 // block) when the solve was already finished and nothing was updated.
 template <typename T>
 __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int nprev, CgCtl &s_c,
-                                             double &s_beta)
+                                             double &s_beta, int bid, int nb)
 {
     const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;
     double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
@@ -312,7 +312,7 @@ __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int npr
             const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
             s_c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
             s_beta = beta;
-            if (blockIdx.x == 0) {
+            if (bid == 0) {
                 CgCtl o = s_c;
                 if (!o.done) o.it = it + 1;   // iterations completed after this one
                 a.ctl[(it + 1) & 1] = o;
@@ -330,7 +330,7 @@ __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int npr
     T *rn = a.rb[(it + 1) & 1], *wn = a.wb[(it + 1) & 1], *sc = a.sb[it & 1];
     const bool first = it == 0;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for_tiles(a.tiles, S, [&](int64_t n) {
+    for_tiles_b(a.tiles, S, bid, nb, [&](int64_t n) {
         int i, j, k;
         decode(g, n, i, j, k);
         T w[3];
@@ -367,7 +367,7 @@ __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int npr
     });
     block_sum<4>(v);
     if (threadIdx.x == 0)
-        for (int q = 0; q < 4; ++q) Pout[(int64_t)blockIdx.x * 4 + q] = v[q];
+        for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
     return false;
 }
 
@@ -383,7 +383,50 @@ __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
     }
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
-    cg_iteration<T>(a, it, gridDim.x, s_c, s_beta);
+    cg_iteration<T>(a, it, gridDim.x, s_c, s_beta, blockIdx.x, gridDim.x);
+}
+
+// One iteration of every solve of a batch in one launch: block b serves
+// instance inst[b] as its block b - off[inst] (each instance's slice starts
+// at a multiple of 8 and has tab[i].blocks blocks), running exactly the
+// single-instance iteration.
+__global__ void __launch_bounds__(256)
+    k_cg_iter_batch(const CgArgs<double> *__restrict__ tab, const int *__restrict__ inst,
+                    const int *__restrict__ off, int it)
+{
+    const int i = inst[blockIdx.x];
+    const CgArgs<double> &a = tab[i];
+    const int bid = blockIdx.x - off[i];
+    if (a.ctl[it & 1].done) {
+        if (bid == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
+        return;
+    }
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    cg_iteration<double>(a, it, a.blocks, s_c, s_beta, bid, a.blocks);
+}
+
+// *flag = 1 if every solve of the batch has finished before iteration it
+__global__ void k_batch_done(const CgArgs<double> *__restrict__ tab, int n, int it, int *flag)
+{
+    __shared__ int s_all;
+    if (threadIdx.x == 0) s_all = 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (!tab[i].ctl[it & 1].done) atomicAnd(&s_all, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = s_all;
+}
+
+void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
+                   int it, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_iter_batch, dim3(total_blocks), dim3(kTile), 0, st, tab, inst, off, it);
+}
+
+void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_done, dim3(1), dim3(256), 0, st, tab, n, it, flag);
 }
 
 // Grid barrier of a cooperative launch (all blocks resident): blocks arrive
@@ -437,7 +480,7 @@ __global__ void __launch_bounds__(256) k_cg_tail(CgArgs<T> a, int it0, unsigned 
     unsigned gen = 0;
     bool ok = true;
     for (int it = it0;; ++it) {
-        if (cg_iteration<T>(a, it, nprev, s_c, s_beta)) break;
+        if (cg_iteration<T>(a, it, nprev, s_c, s_beta, blockIdx.x, gridDim.x)) break;
         nprev = gridDim.x;
         ok = grid_barrier(bar, ++gen);
         if (!ok) break;

@@ -247,3 +247,68 @@ class Graph:
         if getattr(self, "g", None):
             self.lib.ec_graph_destroy(self.g)
             self.g = None
+
+
+class Batch:
+    """Problems of uneven size stepped together (one launch per batched PCG
+    iteration).  All problems must share one stream: create them with
+    Problem(wl, stream=s) for a common torch stream s."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        p0 = self.problems[0]
+        self.lib, self.device, self.stream = p0.lib, p0.device, p0.stream
+        if any(p.stream.cuda_stream != p0.stream.cuda_stream for p in self.problems):
+            raise ValueError("all problems of a batch must share one stream")
+        n = len(self.problems)
+        self._hs = (C.c_void_p * n)(*[p.h.value for p in self.problems])
+        b = C.c_int64()
+        L.check(self.lib.ec_batch_sizes(n, self._hs, C.byref(b)))
+        self.workspace = torch.empty(b.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        out = C.c_void_p()
+        with p0._on_stream():
+            L.check(self.lib.ec_batch_create(n, self._hs,
+                                             C.c_void_p(self.workspace.data_ptr() + off),
+                                             b.value, C.byref(out)))
+        self.b = out
+
+    def _args(self, dt, A):
+        n = len(self.problems)
+        dts = (C.c_double * n)(*[float(d) for d in dt])
+        ptrs = (C.c_void_p * n)(*[a.data_ptr() for a in A])
+        return dts, ptrs
+
+    def step(self, dt, A, opts, m=-1):
+        dts, ptrs = self._args(dt, A)
+        with self.problems[0]._on_stream():
+            L.check(self.lib.ec_batch_step(self.b, int(m), dts, ptrs, C.byref(opts)))
+
+    def run(self, m0, nsteps, dt, A, opts):
+        dts, ptrs = self._args(dt, A)
+        with self.problems[0]._on_stream():
+            L.check(self.lib.ec_batch_run(self.b, int(m0), int(nsteps), dts, ptrs, C.byref(opts)))
+
+    def graph_capture(self, dt, A, opts):
+        dts, ptrs = self._args(dt, A)
+        g = C.c_void_p()
+        with self.problems[0]._on_stream():
+            L.check(self.lib.ec_batch_graph_capture(self.b, dts, ptrs, C.byref(opts),
+                                                    C.byref(g)))
+        return Graph(self.problems[0], g)
+
+    def set_tiles(self, tiles_per_block):
+        L.check(self.lib.ec_batch_set_tiles(self.b, int(tiles_per_block)))
+
+    def autotune(self, cache_path=None):
+        f, us = C.c_int32(), C.c_double()
+        with self.problems[0]._on_stream():
+            L.check(self.lib.ec_batch_autotune(self.b, cache_path.encode() if cache_path else None,
+                                               C.byref(f), C.byref(us)))
+        return f.value, us.value
+
+    def __del__(self):
+        if getattr(self, "b", None):
+            self.lib.ec_batch_destroy(self.b)
+            self.b = None
+
