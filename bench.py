@@ -197,6 +197,75 @@ def adjoint_c5(ec, torch, steps=500, every=50, N=64, rtol=1e-8, check_steps=100)
     return out
 
 
+def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
+    """64 uneven instances (seeded draws: N in [16, 64], sigma = 10^U(5,7),
+    Brauer coefficients within 10 %), each at half its own stability bound,
+    SPE m = 8.  After `warmup` eager batched steps, `steps` replays of one
+    graph holding every instance's step (batched PCG launches, autotuned
+    grids) are timed, then the same steps as 64 per-instance graphs launched
+    one after the other."""
+    import synth
+    wls = synth.batch_workloads(count)
+    s = torch.cuda.Stream()
+    probs = [ec.Problem(w, window_cap=8, stream=s) for w in wls]
+    dts = [0.5 * 2.0 / p.cfl(iters=15, rtol=1e-8) for p in probs]
+    B = ec.Batch(probs)
+    cache = os.path.expanduser("~/.cache/paper_1611_06721_amd/batch_tiles.txt")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    tiles, tuned_us = B.autotune(cache)
+    opts = ec.step_opts(ec.SV_SPE, window=8, rtol=rtol)
+    out = {"workload": f"{count} instances, N in [16, 64], {steps} steps, SPE m=8, rtol {rtol:g}",
+           "edges_total": int(sum(p.n_pad for p in probs)),
+           "autotuned_tiles_per_block": tiles, "batched_iteration_us": round(tuned_us, 2)}
+    for mode in ("batched_graph", "per_instance_graphs"):
+        As = [p.zeros() for p in probs]
+        for p, A in zip(probs, As):
+            p.set_state(A, rtol=rtol)
+        B.run(0, warmup, dts, As, opts)
+        # iteration budget per solve from the last warm-up steps
+        mx = [0, 0]
+        for _ in range(6):
+            for p in probs:
+                p.counters_reset()
+            B.step(dts, As, opts)
+            for p in probs:
+                c = p.counters()
+                mx[0] = max(mx[0], c["iters_src"])
+                mx[1] = max(mx[1], c["iters_cpl"])
+        budgets = [int(1.5 * mx[0]) + 4, int(1.5 * mx[1]) + 8]
+        gopts = ec.step_opts(ec.SV_SPE, window=8, rtol=rtol, graph_iters=tuple(budgets))
+        for p in probs:
+            p.counters_reset()
+        if mode == "batched_graph":
+            graphs = [B.graph_capture(dts, As, gopts)]
+        else:
+            graphs = [p.graph_capture(A, dt, gopts) for p, A, dt in zip(probs, As, dts)]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            for g in graphs:
+                g.launch_raw()
+        e1.record(s)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        cs = [p.counters() for p in probs]
+        del graphs
+        iters = sum(c["iters_src"] + c["iters_cpl"] for c in cs)
+        out[mode] = {"instance_steps_per_s": round(count * steps / (ms * 1e-3), 1),
+                     "batch_steps_per_s": round(steps / (ms * 1e-3), 2),
+                     "ms_per_batch_step": round(ms / steps, 3),
+                     "iters_per_instance_step": round(iters / (count * steps), 3),
+                     "graph_iteration_budget": budgets,
+                     "worst_status": min(c["worst_status"] for c in cs)}
+        log(f"[bench] batch {mode}: {out[mode]['instance_steps_per_s']} instance-steps/s")
+    out["speedup_batched"] = round(out["batched_graph"]["instance_steps_per_s"] /
+                                   out["per_instance_graphs"]["instance_steps_per_s"], 3)
+    del B, probs
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_cg_iteration(ec, torch, G, reps=400):
     """Average duration of one PCG iteration kernel (FP64, every iteration
     active): solves that run exactly 100 and 100 + reps iterations, timed with
@@ -281,6 +350,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 FP64 / FP32-refined runs")
     ap.add_argument("--c3-steps", type=int, default=200)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 64^3 adjoint runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch runs")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the dominant-kernel timing and a 512 MiB device copy "
                          "(the reference for the HBM byte counters)")
@@ -360,6 +430,10 @@ def main():
         log(f"[bench] adjoint 64^3: forward {adj['forward_steps_per_s']} steps/s, backward "
             f"{adj['backward_steps_per_s']} steps/s, fd check {adj['fd_check']}")
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_c4(ec, torch)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_steps, dt)
@@ -392,6 +466,7 @@ def main():
         "probe": extra,
         "precision_128": c3,
         "adjoint_64": adj,
+        "batch_64": batch,
         "cpu_baseline": cpu,
     }
     if "zero" in results and head != "zero":
