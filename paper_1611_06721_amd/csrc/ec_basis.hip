@@ -427,37 +427,33 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
     __syncthreads();
 }
 
-// Deterministic reduction of nvals values over kMdBlocks partial rows into
-// the shared val[] (all threads of the last block).
+// Deterministic reduction of nvals values over the kMdBlocks block partials
+// (stored value-major: part[q * kMdBlocks + block]) into the shared val[]
+// (all threads of the block, blockDim.x = kMdBlocks = 256): every value's
+// partials are one coalesced load per wave, then a fixed-order wave butterfly
+// and a fixed-order sum of the four waves.
 __device__ void reduce_rows(const double *part, int nvals, double *val)
 {
-    __shared__ double tmp[16][17];
-    const int tid = threadIdx.x;
-    const int vq = tid & 15, gq = tid >> 4;     // 16 values x 16 block groups
-    for (int c0 = 0; c0 < nvals; c0 += 16) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        if (c0 + vq < nvals) {
-            for (int b = gq; b < kMdBlocks; b += 64) {
-                const double *P = part + c0 + vq;
-                s0 += P[(int64_t)b * kMdStride];
-                if (b + 16 < kMdBlocks) s1 += P[(int64_t)(b + 16) * kMdStride];
-                if (b + 32 < kMdBlocks) s2 += P[(int64_t)(b + 32) * kMdStride];
-                if (b + 48 < kMdBlocks) s3 += P[(int64_t)(b + 48) * kMdStride];
-            }
+    __shared__ double tmp[kMdStride][4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double r[kMdStride];
+#pragma unroll
+    for (int q = 0; q < kMdStride; ++q)
+        r[q] = (q < nvals && tid < kMdBlocks) ? part[(int64_t)q * kMdBlocks + tid] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kMdStride; ++q) {
+        if (q < nvals) {
+            const double sq = wave_sum(r[q]);
+            if (lane == 0) tmp[q][wv] = sq;
         }
-        tmp[gq][vq] = (s0 + s1) + (s2 + s3);
-        __syncthreads();
-        if (tid < 16 && c0 + tid < nvals) {
-            double t = 0.0;
-            for (int g2 = 0; g2 < 16; ++g2) t += tmp[g2][tid];
-            val[c0 + tid] = t;
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    if (tid < nvals) val[tid] = ((tmp[tid][0] + tmp[tid][1]) + tmp[tid][2]) + tmp[tid][3];
+    __syncthreads();
 }
 
 // -------------------------------------------------------- basis products
-// part[block][i*nb + j] = sum over rows of A_i B_j for p = k (+1 with
+// part[(i*nb + j) * kMdBlocks + block] = sum over the block's rows of A_i B_j for p = k (+1 with
 // a_extra) columns of A and nb <= 4 vectors B.  One wave handles 16 rows per
 // step: lane (m = lane % 16, kq = lane / 16) loads 4 consecutive rows of A
 // column m (and of B_m), so each 16-lane group reads full 128-byte lines;
@@ -505,21 +501,36 @@ __global__ void __launch_bounds__(256) k_multidot(MdArgs a)
     dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     const int64_t n = a.n;
     const int64_t gw = (int64_t)blockIdx.x * 4 + wv, nw = (int64_t)gridDim.x * 4;
-    for (int64_t r0 = gw * 16; r0 < n; r0 += nw * 16) {
-        const int64_t row = r0 + kq * 4;
-        double av0[4], av1[4], bv[4];
-        load4(cA0, row, n, av0);
-        load4(cB, row, n, bv);
+    // two 16-row groups per iteration: every load of both groups is issued
+    // before the matrix-core work that consumes them
+    for (int64_t r0 = gw * 16; r0 < n; r0 += 2 * nw * 16) {
+        const int64_t rowa = r0 + kq * 4, rowb = r0 + nw * 16 + kq * 4;
+        double aa[4], ab[4], ba[4], bb[4];
+        load4(cA0, rowa, n, aa);
+        load4(cB, rowa, n, ba);
+        load4(cA0, rowb, n, ab);
+        load4(cB, rowb, n, bb);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) bv[s] *= bs;
+        for (int s = 0; s < 4; ++s) {
+            ba[s] *= bs;
+            bb[s] *= bs;
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av0[s], bv[s], acc0, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[s], ba[s], acc0, 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ab[s], bb[s], acc0, 0, 0, 0);
         if (p > 16) {
-            load4(cA1, row, n, av1);
+            double a1[4], a2[4];
+            load4(cA1, rowa, n, a1);
+            load4(cA1, rowb, n, a2);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1[s], bv[s], acc1, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], ba[s], acc1, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[s], bb[s], acc1, 0, 0, 0);
         }
     }
     // D layout (gfx950): lane l, element s holds C[4*s + l/16][l % 16]
@@ -537,7 +548,7 @@ __global__ void __launch_bounds__(256) k_multidot(MdArgs a)
         for (int t = 0; t < nvals; ++t) {
             const int i = t / nb, j = t - i * nb;
             const double s = ((red[0][i][j] + red[1][i][j]) + red[2][i][j]) + red[3][i][j];
-            a.part[(int64_t)blockIdx.x * kMdStride + t] = s;
+            a.part[(int64_t)t * kMdBlocks + blockIdx.x] = s;     // value-major
         }
     }
 }
@@ -615,10 +626,12 @@ __global__ void __launch_bounds__(256) k_lincomb(LcArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double *P = a.part + (int64_t)blockIdx.x * kMdStride;
-        for (int i = 0; i < nv; ++i) P[i] = ((lds[i][0] + lds[i][1]) + lds[i][2]) + lds[i][3];
+        double *P = a.part + blockIdx.x;                         // value-major
+        for (int i = 0; i < nv; ++i)
+            P[(int64_t)i * kMdBlocks] = ((lds[i][0] + lds[i][1]) + lds[i][2]) + lds[i][3];
         for (int q = 0; q < 3; ++q)
-            P[nv + q] = ((lds[kMaxWin + q][0] + lds[kMaxWin + q][1]) + lds[kMaxWin + q][2]) +
+            P[(int64_t)(nv + q) * kMdBlocks] =
+                ((lds[kMaxWin + q][0] + lds[kMaxWin + q][1]) + lds[kMaxWin + q][2]) +
                         lds[kMaxWin + q][3];
     }
 }
@@ -668,7 +681,20 @@ __global__ void __launch_bounds__(256)
     k_small(SeqDev *sq, int op, const double *part, int nvals, double tol, ec_solve_info *info)
 {
     __shared__ double val[kMdStride];
-    if (part) reduce_rows(part, nvals, val);
+    // exactly the values the producing product kernel wrote (state before the op)
+    int nv = nvals;
+    switch (op) {
+    case OP_SPE_START: nv = sq->k; break;                 // q^T b
+    case OP_POD_START: nv = sq->count; break;             // X^T b
+    case OP_SPE_PUSH1: nv = sq->k + 1; break;             // [q, x]^T x
+    case OP_SPE_PUSH2: nv = sq->ncol_md + 3; break;       // q^T w and three norms
+    case OP_SPE_PUSH3: nv = 3; break;                     // norms only
+    case OP_SPE_PUSH4: nv = sq->ncol_md; break;           // q^T (K_n + eta D^T D) t
+    case OP_POD_PUSH: nv = 2 * sq->npush; break;          // X^T [x, K x]
+    default: break;
+    }
+    nv = nv < 0 ? 0 : (nv > nvals ? nvals : nv);
+    if (part) reduce_rows(part, nv, val);
     __syncthreads();
     small_op(sq, op, val, tol, info);
 }
