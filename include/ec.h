@@ -176,6 +176,15 @@ int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y);
  * POD (eqs. 11-14) is unaffected: its truncation drops those directions. */
 int32_t ec_set_gauge_penalty(ec_handle h, double factor);
 
+/* PCG iteration kernel of the handle's FP64 and FP32 solves (eq. 9): 0 the
+ * node-parallel kernel (one thread per node, 24-point stencil from global
+ * memory), 1 the 2.5D kernel (a 256-node column per block marching over a
+ * chunk of planes, the stencil input staged once per plane in LDS), -1 the
+ * default choice (2.5D from 96^3 nodes).  Both compute the same iteration
+ * (results agree to rounding of the partial sums).  EC_ERR_ARG for another
+ * kind or a grid the 2.5D grid does not fit. */
+int32_t ec_set_pcg_kernel(ec_handle h, int32_t kind);
+
 /* Linear-independence threshold of the SPE window (eq. 10 asks for linearly
  * independent solutions without a number): a pushed solution x joins the
  * basis only if its part orthogonal to the basis exceeds tol * ||x||.

@@ -75,6 +75,7 @@ SIGNATURES = {
     "ec_apply": (C.c_int32, [_H, C.c_int32, _P, _P]),
     "ec_set_gauge_penalty": (C.c_int32, [_H, C.c_double]),
     "ec_set_dependency_tol": (C.c_int32, [_H, C.c_double]),
+    "ec_set_pcg_kernel": (C.c_int32, [_H, C.c_int32]),
     "ec_history_reset": (C.c_int32, [_H, C.c_int32]),
     "ec_history_push": (C.c_int32, [_H, C.c_int32, C.c_int32, C.c_int32, _P]),
     "ec_start_vector": (C.c_int32, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,

@@ -82,6 +82,9 @@ struct ec_problem {
     double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr;
     unsigned *bar = nullptr;     // grid-barrier counters of the PCG tail kernel
     int tail_blocks = 0;         // cooperative tail grid (0: no tail available)
+    // 2.5D PCG iteration (large grids): column width, planes per block, tile
+    // counts and its grid; used while cg_blocks == grid25
+    int t25 = 0, kb25 = 0, nti25 = 0, ntj25 = 0, ntk25 = 0, grid25 = 0, node_blocks = 0;
     int seq_method[EC_NSEQ], seq_win[EC_NSEQ], seq_kmax[EC_NSEQ];
     double seq_eps[EC_NSEQ];
     int hint[EC_NSEQ];
@@ -382,6 +385,38 @@ extern "C" int32_t ec_sizes(ec_handle h, int32_t window_cap, int64_t *n_padded, 
 
 // Grid of the node kernels: one tile of 256 nodes per block up to kMaxBlocks
 // (then a block sweeps several tiles); a multiple of 8 for the XCD mapping.
+// Shape of the 2.5D iteration: the column width with the least idle threads
+// (TI x 256/TI nodes), then the fewest planes per block (>= 8) that keep the
+// grid within kMaxBlocks.  Returns false when the grid is too small to fill
+// the chip with it.
+static bool plan_25(ec_problem *h, bool force)
+{
+    const int nx = h->g.nx, ny = h->g.ny, nz = h->g.nz;
+    if (!force && (int64_t)nx * ny * nz < (int64_t)96 * 96 * 96) return false;
+    double best = 1e300;
+    int bt = 0;
+    for (int ti : {64, 32, 16}) {
+        const int tj = 256 / ti;
+        const int64_t cover = (int64_t)((nx + ti - 1) / ti) * ti * (((ny + tj - 1) / tj) * tj);
+        const double waste = (double)cover / ((double)nx * ny);
+        if (waste < best - 1e-9) {
+            best = waste;
+            bt = ti;
+        }
+    }
+    const int tj = 256 / bt, nti = (nx + bt - 1) / bt, ntj = (ny + tj - 1) / tj;
+    int kb = std::min(8, nz), ntk = 0;
+    for (;; kb = std::min(nz, kb * 2)) {
+        ntk = (nz + kb - 1) / kb;
+        if (align_up((int64_t)nti * ntj * ntk, 8) <= kMaxBlocks || kb >= nz) break;
+    }
+    const int64_t grid = align_up((int64_t)nti * ntj * ntk, 8);
+    if (grid > kMaxBlocks) return false;
+    h->t25 = bt; h->kb25 = kb; h->nti25 = nti; h->ntj25 = ntj; h->ntk25 = ntk;
+    h->grid25 = (int)grid;
+    return true;
+}
+
 static int choose_blocks(ec_problem *h)
 {
     const int64_t tiles = (h->S + kTile - 1) / kTile;
@@ -438,7 +473,8 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
     for (hipEvent_t &e : h->ev)
         if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->tiles = (int)((h->S + kTile - 1) / kTile);
-    h->cg_blocks = choose_blocks(h);
+    h->node_blocks = choose_blocks(h);
+    h->cg_blocks = plan_25(h, false) ? h->grid25 : h->node_blocks;
     h->tail_blocks = cg_tail_blocks<double>();
     h->bound = true;
     return EC_OK;
@@ -675,6 +711,14 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
     return launch_check(h, "cg");
 }
 
+template <typename T>
+static void set_25(const ec_problem *h, CgArgs<T> &a)
+{
+    const bool on = h->t25 > 0 && h->cg_blocks == h->grid25;
+    a.t25 = on ? h->t25 : 0;
+    a.kb25 = h->kb25; a.nti25 = h->nti25; a.ntj25 = h->ntj25; a.ntk25 = h->ntk25;
+}
+
 static CgArgs<double> cg64_args(ec_problem *h, int seq, const double *b, const double *bscale,
                                 double *x, const ec_solve_opts *o, ec_solve_info *info)
 {
@@ -698,6 +742,7 @@ static CgArgs<double> cg64_args(ec_problem *h, int seq, const double *b, const d
     a.tiles = h->tiles;
     a.blocks = h->cg_blocks;
     a.bar = h->bar;
+    set_25(h, a);
     return a;
 }
 
@@ -768,6 +813,7 @@ static int32_t run_refined(ec_problem *h, int seq, const double *b, const double
         a.skip = &h->ctrl_d->refine_done;
         a.tiles = h->tiles;
         a.blocks = h->cg_blocks;
+        set_25(h, a);
         cg_init<float>(a, st);
         int issued = 0;
         int32_t rc = cg_iterate<float>(h, a, seq, false, &issued);
@@ -846,6 +892,23 @@ extern "C" int32_t ec_set_gauge_penalty(ec_handle h, double factor)
         return fail(h, EC_ERR_ARG, "factor must be finite and >= 0");
     // histories built with another weight start anew at their next use
     h->gauge_rel = factor;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_set_pcg_kernel(ec_handle h, int32_t kind)
+{
+    NEED_BOUND(h);
+    if (kind < -1 || kind > 1) return fail(h, EC_ERR_ARG, "kind must be -1, 0 or 1");
+    h->t25 = 0;
+    if (kind == 0 || (kind == -1 && !plan_25(h, false))) {
+        h->cg_blocks = h->node_blocks;
+        return EC_OK;
+    }
+    if (!plan_25(h, true)) {
+        h->cg_blocks = h->node_blocks;
+        return fail(h, EC_ERR_ARG, "the 2.5D kernel does not fit this grid");
+    }
+    h->cg_blocks = h->grid25;
     return EC_OK;
 }
 

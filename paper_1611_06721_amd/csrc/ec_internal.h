@@ -140,6 +140,10 @@ struct CgArgs {
     int tiles;
     int blocks;
     unsigned *bar;           // grid-barrier counters of the tail kernel (9 x kBarStride)
+    // 2.5D iteration kernel (large grids): TI of the node column (0: the
+    // node-parallel kernel), planes per block and the tile counts; the 2.5D
+    // grid is `blocks`
+    int t25, kb25, nti25, ntj25, ntk25;
 };
 
 // grid barrier: counter words kBarStride apart (separate 128-byte lines);

@@ -429,6 +429,174 @@ void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t
     hipLaunchKernelGGL(k_batch_done, dim3(1), dim3(256), 0, st, tab, n, it, flag);
 }
 
+// Prologue of an iteration kernel: reduce the nprev partials of the previous
+// iteration (same order in every block), decide; block bid 0 passes the
+// record on.  True when the solve was already finished.
+template <typename T>
+__device__ __forceinline__ bool cg_begin(const CgArgs<T> &a, int it, int nprev, CgCtl &s_c,
+                                         double &s_beta, int bid)
+{
+    const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;
+    double t[4];
+    sum_part(Pin, nprev, t);
+    if (threadIdx.x == 0) {
+        double beta;
+        const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
+        s_c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
+        s_beta = beta;
+        if (bid == 0) {
+            CgCtl o = s_c;
+            if (!o.done) o.it = it + 1;
+            a.ctl[(it + 1) & 1] = o;
+        }
+    }
+    __syncthreads();
+    return s_c.done != 0;
+}
+
+// One PCG iteration for large grids (2.5D blocking).  Block b owns the node
+// column [i0, i0+TI) x [j0, j0+TJ) (TI*TJ = 256 threads, one node each) and
+// the planes [k0, k0+kb).  The transformed input
+//   t = D^-1 (r - alpha (w + beta s))
+// of every plane is computed once, with a one-node halo, into a ring of three
+// LDS planes, and the 24-point curl-curl of the node reads it from there
+// instead of issuing 72 global loads.  Outputs, partial sums and the record
+// protocol are those of the node-parallel iteration; the grid must equal
+// a.blocks (8-aligned, blocks past the last column only write zero partials).
+template <typename T, int TI>
+__global__ void __launch_bounds__(256)
+    k_cg_iter25(CgArgs<T> a, int it, int kb, int nti, int ntj, int ntk)
+{
+    constexpr int TJ = 256 / TI, LI = TI + 2, LJ = TJ + 2, LP = LI * LJ;
+    __shared__ T lt[3][3][LP];
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    if (a.skip && *a.skip) return;
+    if (a.ctl[it & 1].done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
+        return;
+    }
+    if (cg_begin<T>(a, it, gridDim.x, s_c, s_beta, blockIdx.x)) return;
+    const Geo &g = a.g;
+    const int64_t S = g.S, oj = g.px, ok = (int64_t)g.px * g.py;
+    const T dd[3] = {(T)g.dinv[0], (T)g.dinv[1], (T)g.dinv[2]};
+    const T ta = (T)s_c.alpha, tb = (T)s_beta;
+    const bool first = it == 0;
+    const T *rc = a.rb[it & 1], *wc = a.wb[it & 1], *sp = a.sb[(it + 1) & 1];
+    T *rn = a.rb[(it + 1) & 1], *wn = a.wb[(it + 1) & 1], *sc = a.sb[it & 1];
+    // XCD-contiguous ranges of (k-chunk, j, i) tiles
+    const int total = nti * ntj * ntk, tpx = (total + 7) >> 3;
+    const int L = (blockIdx.x & 7) * tpx + (blockIdx.x >> 3);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (L < total) {
+        const int ti = L % nti, tj = (L / nti) % ntj, tk = L / (nti * ntj);
+        const int i0 = ti * TI, j0 = tj * TJ, k0 = tk * kb, k1 = min(k0 + kb, g.nz);
+        const int lx = threadIdx.x % TI, ly = threadIdx.x / TI;
+        const int i = i0 + lx, j = j0 + ly;
+        const bool own = i < g.nx && j < g.ny;
+        // t of plane kk into ring slot kk % 3 (zero outside the grid)
+        auto load_plane = [&](int kk) {
+            T(*dst)[LP] = lt[((kk % 3) + 3) % 3];
+            for (int q = threadIdx.x; q < LP; q += 256) {
+                const int li = q % LI, lj = q / LI;
+                const int ii = i0 - 1 + li, jj = j0 - 1 + lj;
+                T t0 = (T)0, t1 = (T)0, t2 = (T)0;
+                if (kk >= 0 && kk <= g.nz && ii >= 0 && ii < g.px && jj >= 0 && jj < g.py) {
+                    const int64_t n = kk * ok + (int64_t)jj * oj + ii;
+                    T tt[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int64_t ix = c * S + n;
+                        const T u = first ? wc[ix] : wc[ix] + tb * sp[ix];
+                        tt[c] = dd[c] * (rc[ix] - ta * u);
+                    }
+                    t0 = tt[0]; t1 = tt[1]; t2 = tt[2];
+                }
+                dst[0][q] = t0;
+                dst[1][q] = t1;
+                dst[2][q] = t2;
+            }
+        };
+        load_plane(k0 - 1);
+        load_plane(k0);
+        const int lc = (ly + 1) * LI + (lx + 1);
+        const T wx = (T)g.wx, wy = (T)g.wy, wz = (T)g.wz;
+        for (int k = k0; k < k1; ++k) {
+            // the node's own values of plane k first: their loads overlap the
+            // halo loads of plane k + 1 (neither waits for the barrier)
+            const int64_t n = k * ok + (int64_t)j * oj + i;
+            T orv[3] = {(T)0, (T)0, (T)0}, owv[3] = {(T)0, (T)0, (T)0};
+            T osp[3] = {(T)0, (T)0, (T)0}, opv[3] = {(T)0, (T)0, (T)0};
+            if (own) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t ix = c * S + n;
+                    orv[c] = rc[ix];
+                    owv[c] = wc[ix];
+                    if (!first) {
+                        osp[c] = sp[ix];
+                        opv[c] = a.p[ix];
+                    }
+                }
+            }
+            load_plane(k + 1);
+            __syncthreads();
+            if (own) {
+                const T(*pm)[LP] = lt[((k - 1) % 3 + 3) % 3];
+                const T(*p0)[LP] = lt[k % 3];
+                const T(*pp)[LP] = lt[(k + 1) % 3];
+                const int di = 1, dj = LI;
+                const T x0 = p0[0][lc], x_kp = pp[0][lc], x_km = pm[0][lc],
+                        x_im_kp = pp[0][lc - di], x_im = p0[0][lc - di], x_jp = p0[0][lc + dj],
+                        x_jm = p0[0][lc - dj], x_im_jp = p0[0][lc + dj - di];
+                const T y0 = p0[1][lc], y_kp = pp[1][lc], y_km = pm[1][lc], y_jm = p0[1][lc - dj],
+                        y_jm_kp = pp[1][lc - dj], y_ip = p0[1][lc + di],
+                        y_ip_jm = p0[1][lc + di - dj], y_im = p0[1][lc - di];
+                const T z0 = p0[2][lc], z_jp = p0[2][lc + dj], z_jp_km = pm[2][lc + dj],
+                        z_km = pm[2][lc], z_jm = p0[2][lc - dj], z_ip = p0[2][lc + di],
+                        z_ip_km = pm[2][lc + di], z_im = p0[2][lc - di];
+                const T Fx = y0 + z_jp - y_kp - z0;
+                const T Fx_km = y_km + z_jp_km - y0 - z_km;
+                const T Fx_jm = y_jm + z0 - y_jm_kp - z_jm;
+                const T Fy = z0 + x_kp - z_ip - x0;
+                const T Fy_km = z_km + x0 - z_ip_km - x_km;
+                const T Fy_im = z_im + x_im_kp - z0 - x_im;
+                const T Fz = x0 + y_ip - x_jp - y0;
+                const T Fz_jm = x_jm + y_ip_jm - x0 - y_jm;
+                const T Fz_im = x_im + y0 - x_im_jp - y_im;
+                const T q[3] = {wz * (Fz - Fz_jm) - wy * (Fy - Fy_km),
+                                wx * (Fx - Fx_km) - wz * (Fz - Fz_im),
+                                wy * (Fy - Fy_im) - wx * (Fx - Fx_jm)};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t ix = c * S + n;
+                    const T d = dd[c];
+                    const T rv = orv[c], wv = owv[c];
+                    const T si = first ? wv : wv + tb * osp[c];
+                    const T pi = first ? d * rv : d * rv + tb * opv[c];
+                    a.x[ix] += ta * pi;
+                    a.p[ix] = pi;
+                    sc[ix] = si;
+                    const T r1 = rv - ta * si;
+                    rn[ix] = r1;
+                    const T w1 = edge_cls(g, c, i, j, k, n) == 2 ? q[c] : (T)0;
+                    wn[ix] = w1;
+                    const double u1 = (double)d * (double)r1;
+                    v[0] += u1 * (double)r1;
+                    v[1] += (double)w1 * u1;
+                    v[2] += (double)r1 * (double)r1;
+                }
+            }
+            __syncthreads();           // the next load overwrites plane k - 1
+        }
+    }
+    block_sum<4>(v);
+    if (threadIdx.x == 0) {
+        double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
+        for (int q = 0; q < 4; ++q) Pout[(int64_t)blockIdx.x * 4 + q] = v[q];
+    }
+}
+
 // Grid barrier of a cooperative launch (all blocks resident): blocks arrive
 // on one counter per group of eight (block b in group b % 8), the last of a
 // group bumps the top counter, every block waits for the top counter to
@@ -552,6 +720,18 @@ void cg_init(const CgArgs<T> &a, hipStream_t st)
 template <typename T>
 void cg_iter(const CgArgs<T> &a, int i, hipStream_t st)
 {
+    if (a.t25 > 0) {
+        if (a.t25 == 64)
+            hipLaunchKernelGGL((k_cg_iter25<T, 64>), dim3(a.blocks), dim3(kTile), 0, st, a, i,
+                               a.kb25, a.nti25, a.ntj25, a.ntk25);
+        else if (a.t25 == 32)
+            hipLaunchKernelGGL((k_cg_iter25<T, 32>), dim3(a.blocks), dim3(kTile), 0, st, a, i,
+                               a.kb25, a.nti25, a.ntj25, a.ntk25);
+        else
+            hipLaunchKernelGGL((k_cg_iter25<T, 16>), dim3(a.blocks), dim3(kTile), 0, st, a, i,
+                               a.kb25, a.nti25, a.ntj25, a.ntk25);
+        return;
+    }
     hipLaunchKernelGGL(k_cg_iter<T>, dim3(a.blocks), dim3(kTile), 0, st, a, i);
 }
 template <typename T>

@@ -131,6 +131,10 @@ class Problem:
         with self._on_stream():
             self._chk(self.lib.ec_set_gauge_penalty(self.h, factor))
 
+    def set_pcg_kernel(self, kind):
+        """0 node-parallel, 1 2.5D (LDS-staged), -1 default for the grid size."""
+        self._chk(self.lib.ec_set_pcg_kernel(self.h, int(kind)))
+
     def set_dependency_tol(self, tol):
         with self._on_stream():
             self._chk(self.lib.ec_set_dependency_tol(self.h, tol))
