@@ -291,20 +291,6 @@ def time_cg_iteration(ec, torch, G, reps=400):
     return 1e3 * (long_ - short) / reps
 
 
-def time_spmv(ec, torch, G, reps=50):
-    x = torch.randn(G.n_pad, dtype=torch.float64, device=G.device)
-    y = G.zeros()
-    G.apply(ec.OP_KN, x, out=y)
-    s = G.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        G.apply(ec.OP_KN, x, out=y)
-    e1.record(s)
-    e1.synchronize()
-    return 1e3 * e0.elapsed_time(e1) / reps
-
-
 def traffic_record(kernel, workload):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled by a
     copy kernel) if recorded for the current kernel sources, else None."""
@@ -371,12 +357,16 @@ def main():
     G = ec.Problem(wl, window_cap=20)
     if args.roofline_only:
         cg_us = time_cg_iteration(ec, torch, G)
+        G128 = ec.Problem(synth.nonlinear(128), window_cap=1)
+        cg128_us = time_cg_iteration(ec, torch, G128, reps=200)
+        del G128
         x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=G.device)
         y = torch.empty_like(x)
         torch.cuda.synchronize()
         y.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"kernel": "k_cg_iter<double>", "avg_us": round(cg_us, 3),
+        print(json.dumps({"k_cg_iter<double>@48^3_us": round(cg_us, 3),
+                          "k_cg_iter25<double,64>@128^3_us": round(cg128_us, 3),
                           "copy_bytes_each_way": COPY_BYTES}), flush=True)
         return
     lam = G.cfl(iters=60, rtol=1e-10)
@@ -402,20 +392,26 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "kernel": "k_cg_iter<double> (one PCG iteration)",
                 "avg_us": round(cg_us, 3), "bytes_per_launch": cg_bytes}
-    spmv_us = time_spmv(ec, torch, G)
-    extra = {"spmv_48": {"avg_us_incl_mask": round(spmv_us, 3)}}
+    extra = {}
     del G
     torch.cuda.empty_cache()
 
     if not args.no_probe:
+        os.makedirs(os.path.expanduser("~/.cache/paper_1611_06721_amd"), exist_ok=True)
         # HBM-resident sizes: the working set exceeds the 256 MB Infinity Cache
+        # (the 2.5D kernel is the default on these grids)
         for Np in (128, 256):
             Gp = ec.Problem(synth.nonlinear(Np), window_cap=1)
+            tuned = Gp.tune_pcg(os.path.expanduser("~/.cache/paper_1611_06721_amd/pcg_tiling.txt"))
             nn = 3 * Np * (Np + 1) ** 2
             us = time_cg_iteration(ec, torch, Gp, reps=60 if Np == 256 else 200)
-            extra[f"cg_iter_{Np}"] = {"avg_us": round(us, 2),
+            extra[f"cg_iter_{Np}"] = {"kernel": (f"k_cg_iter25<double,{tuned[0]}> (2.5D, LDS-staged, "
+                                                 f"{tuned[1]} planes per block)" if tuned[0]
+                                                 else "k_cg_iter<double> (node-parallel)"),
+                                      "avg_us": round(us, 2),
                                       "achieved_GBs": round(80.0 * nn / (us * 1e-6) / 1e9, 1),
-                                      "frac": round(80.0 * nn / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+                                      "frac": round(80.0 * nn / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                                      "traffic": traffic_record("k_cg_iter25", f"{Np}^3")}
             del Gp
             torch.cuda.empty_cache()
             log(f"[bench] probe {Np}^3: cg iteration {us:.1f} us")
@@ -459,7 +455,7 @@ def main():
                                     "prev": "previous solution", "zero": "zero"}[head],
                    "graph": True},
         "iters_per_step": round(r["iters_per_step"], 3),
-        "spmv_hbm_gbs": round(achieved, 2),
+        "spmv_hbm_gbs": round(achieved, 2),      # the SpMV is fused into the PCG kernel
         "methods": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in results.items()},
         "roofline": roofline,

@@ -185,6 +185,16 @@ int32_t ec_set_gauge_penalty(ec_handle h, double factor);
  * kind or a grid the 2.5D grid does not fit. */
 int32_t ec_set_pcg_kernel(ec_handle h, int32_t kind);
 
+/* Autotuner of the handle's FP64/FP32 PCG iteration kernel: times one
+ * iteration (every iteration active, scratch vectors) for the node-parallel
+ * kernel and the 2.5D kernel with columns of 16x16, 32x8 and 64x4 nodes and
+ * 4, 8, 16 or 32 planes per block (grids within the block limit), and keeps
+ * the fastest.  With cache_path it first looks for a pick recorded for this
+ * device and grid and appends new picks (one text line each).  Outputs:
+ * column width (0 = node-parallel), planes per block, microseconds per
+ * iteration.  The handle's stepping state is untouched. */
+int32_t ec_tune_pcg(ec_handle h, const char *cache_path, int32_t *ti, int32_t *kb, double *us);
+
 /* Linear-independence threshold of the SPE window (eq. 10 asks for linearly
  * independent solutions without a number): a pushed solution x joins the
  * basis only if its part orthogonal to the basis exceeds tol * ||x||.

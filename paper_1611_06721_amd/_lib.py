@@ -76,6 +76,8 @@ SIGNATURES = {
     "ec_set_gauge_penalty": (C.c_int32, [_H, C.c_double]),
     "ec_set_dependency_tol": (C.c_int32, [_H, C.c_double]),
     "ec_set_pcg_kernel": (C.c_int32, [_H, C.c_int32]),
+    "ec_tune_pcg": (C.c_int32, [_H, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_double)]),
     "ec_history_reset": (C.c_int32, [_H, C.c_int32]),
     "ec_history_push": (C.c_int32, [_H, C.c_int32, C.c_int32, C.c_int32, _P]),
     "ec_start_vector": (C.c_int32, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,

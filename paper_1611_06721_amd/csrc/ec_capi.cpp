@@ -385,17 +385,20 @@ extern "C" int32_t ec_sizes(ec_handle h, int32_t window_cap, int64_t *n_padded, 
 
 // Grid of the node kernels: one tile of 256 nodes per block up to kMaxBlocks
 // (then a block sweeps several tiles); a multiple of 8 for the XCD mapping.
-// Shape of the 2.5D iteration: the column width with the least idle threads
-// (TI x 256/TI nodes), then the fewest planes per block (>= 8) that keep the
-// grid within kMaxBlocks.  Returns false when the grid is too small to fill
-// the chip with it.
-static bool plan_25(ec_problem *h, bool force)
+// Shape of the 2.5D iteration.  Column width TI (x 256/TI nodes): least
+// idle threads, the widest on ties (contiguous rows along i beat a smaller
+// halo: 128^3 measured 151 us at 64x4 vs 168 us at 16x16); then the fewest
+// planes per block (>= 8) that keep the grid within kMaxBlocks.
+// ti / kb > 0 force a shape.  Returns false when it does not fit (or, without
+// force, when the grid is too small to fill the chip with it).
+static bool plan_25(ec_problem *h, bool force, int ti_want = 0, int kb_want = 0)
 {
     const int nx = h->g.nx, ny = h->g.ny, nz = h->g.nz;
     if (!force && (int64_t)nx * ny * nz < (int64_t)96 * 96 * 96) return false;
     double best = 1e300;
     int bt = 0;
     for (int ti : {64, 32, 16}) {
+        if (ti_want && ti != ti_want) continue;
         const int tj = 256 / ti;
         const int64_t cover = (int64_t)((nx + ti - 1) / ti) * ti * (((ny + tj - 1) / tj) * tj);
         const double waste = (double)cover / ((double)nx * ny);
@@ -404,11 +407,12 @@ static bool plan_25(ec_problem *h, bool force)
             bt = ti;
         }
     }
+    if (!bt) return false;
     const int tj = 256 / bt, nti = (nx + bt - 1) / bt, ntj = (ny + tj - 1) / tj;
-    int kb = std::min(8, nz), ntk = 0;
+    int kb = kb_want > 0 ? std::min(kb_want, nz) : std::min(8, nz), ntk = 0;
     for (;; kb = std::min(nz, kb * 2)) {
         ntk = (nz + kb - 1) / kb;
-        if (align_up((int64_t)nti * ntj * ntk, 8) <= kMaxBlocks || kb >= nz) break;
+        if (align_up((int64_t)nti * ntj * ntk, 8) <= kMaxBlocks || kb >= nz || kb_want > 0) break;
     }
     const int64_t grid = align_up((int64_t)nti * ntj * ntk, 8);
     if (grid > kMaxBlocks) return false;
@@ -909,6 +913,106 @@ extern "C" int32_t ec_set_pcg_kernel(ec_handle h, int32_t kind)
         return fail(h, EC_ERR_ARG, "the 2.5D kernel does not fit this grid");
     }
     h->cg_blocks = h->grid25;
+    return EC_OK;
+}
+
+// One FP64 PCG iteration of the handle's current kernel, every iteration
+// active (a zero-start solve of the source into scratch vectors).
+static int32_t time_pcg_iteration(ec_problem *h, double *us)
+{
+    ec_solve_opts o{};
+    o.rtol = 1e-300;
+    o.maxit = 1 << 30;
+    CgArgs<double> a = cg64_args(h, EC_SEQ_USER, h->xs_d, &h->ctrl_d->one, h->t4, &o, nullptr);
+    a.ctrl = nullptr;
+    cg64_init(h, a, START_ZERO);
+    const int warm = 3, reps = 20;
+    for (int it = 0; it < warm; ++it) cg_iter<double>(a, it, h->st);
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    HIP_TRY(h, hipEventRecord(e0, h->st));
+    for (int it = warm; it < warm + reps; ++it) cg_iter<double>(a, it, h->st);
+    HIP_TRY(h, hipEventRecord(e1, h->st));
+    HIP_TRY(h, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us = 1e3 * ms / reps;
+    return launch_check(h, "pcg timing");
+}
+
+extern "C" int32_t ec_tune_pcg(ec_handle h, const char *cache_path, int32_t *ti_out,
+                               int32_t *kb_out, double *us_out)
+{
+    NEED_BOUND(h);
+    std::string sig;
+    {
+        hipDeviceProp_t prop{};
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            sig += prop.gcnArchName;
+        sig += ":" + std::to_string(h->g.nx) + "x" + std::to_string(h->g.ny) + "x" +
+               std::to_string(h->g.nz);
+    }
+    auto apply = [&](int ti, int kb) -> bool {
+        h->t25 = 0;
+        if (ti == 0) {
+            h->cg_blocks = h->node_blocks;
+            return true;
+        }
+        if (!plan_25(h, true, ti, kb)) {
+            h->cg_blocks = h->node_blocks;
+            return false;
+        }
+        h->cg_blocks = h->grid25;
+        return true;
+    };
+    int best_ti = -1, best_kb = 0;
+    double best_us = 1e300;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[1024], key[900];
+            int ti = 0, kb = 0;
+            double us = 0.0;
+            while (std::fgets(line, sizeof line, f))
+                if (std::sscanf(line, "ec-pcg-tiling %899s %d %d %lf", key, &ti, &kb, &us) == 4 &&
+                    sig == key) {
+                    best_ti = ti; best_kb = kb; best_us = us;
+                }
+            std::fclose(f);
+        }
+        if (best_ti >= 0 && apply(best_ti, best_kb)) {
+            if (ti_out) *ti_out = best_ti;
+            if (kb_out) *kb_out = best_kb;
+            if (us_out) *us_out = best_us;
+            return EC_OK;
+        }
+    }
+    best_ti = 0;
+    best_us = 1e300;
+    for (int ti : {0, 16, 32, 64})
+        for (int kb : {4, 8, 16, 32}) {
+            if (ti == 0 && kb != 4) continue;           // node-parallel: one candidate
+            if (!apply(ti, kb)) continue;
+            double us = 0.0;
+            int32_t rc = time_pcg_iteration(h, &us);
+            if (rc) return rc;
+            if (us < best_us) {
+                best_us = us; best_ti = ti; best_kb = ti ? h->kb25 : 0;
+            }
+        }
+    apply(best_ti, best_kb);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "ec-pcg-tiling %s %d %d %.4f\n", sig.c_str(), best_ti, best_kb, best_us);
+            std::fclose(f);
+        }
+    }
+    if (ti_out) *ti_out = best_ti;
+    if (kb_out) *kb_out = best_kb;
+    if (us_out) *us_out = best_us;
     return EC_OK;
 }
 

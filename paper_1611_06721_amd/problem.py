@@ -135,6 +135,15 @@ class Problem:
         """0 node-parallel, 1 2.5D (LDS-staged), -1 default for the grid size."""
         self._chk(self.lib.ec_set_pcg_kernel(self.h, int(kind)))
 
+    def tune_pcg(self, cache_path=None):
+        """(column width or 0, planes per block, us per iteration) of the
+        fastest PCG iteration kernel for this grid (applied to the handle)."""
+        ti, kb, us = C.c_int32(), C.c_int32(), C.c_double()
+        with self._on_stream():
+            self._chk(self.lib.ec_tune_pcg(self.h, cache_path.encode() if cache_path else None,
+                                           C.byref(ti), C.byref(kb), C.byref(us)))
+        return ti.value, kb.value, us.value
+
     def set_dependency_tol(self, tol):
         with self._on_stream():
             self._chk(self.lib.ec_set_dependency_tol(self.h, tol))

@@ -552,3 +552,24 @@ def test_tiled_and_node_kernels_agree_at_128(ec, oracle_mod):
     for x in xs:
         assert np.linalg.norm(bn - O.kn(x)) <= 2e-10 * np.linalg.norm(bn)
     assert np.linalg.norm(xs[0] - xs[1]) <= 1e-8 * np.linalg.norm(xs[1])
+
+
+def test_pcg_autotuner_cache(ec, oracle_mod, tmp_path):
+    """ec_tune_pcg picks a kernel for the grid, records it, and a second
+    handle of the same grid gets the recorded pick without timing; solves
+    with the tuned kernel still match the oracle."""
+    wl = WORKLOADS["nl16"]()
+    O = oracle_mod.Problem(wl)
+    cache = str(tmp_path / "pcg.txt")
+    G = ec.Problem(wl, window_cap=1)
+    ti, kb, us = G.tune_pcg(cache)
+    assert ti in (0, 16, 32, 64) and us > 0
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("ec-pcg-tiling ")
+    G2 = ec.Problem(wl, window_cap=1)
+    assert G2.tune_pcg(cache)[:2] == (ti, kb)
+    assert len(open(cache).read().splitlines()) == 1
+    b = O.kcnT(synth.random_vector(O.n_pad, O.C, 4))
+    x = G2.solve(G2.tensor(b), method=ec.SV_ZERO, rtol=1e-12).cpu().numpy()
+    xo, *_ = O.cg(b, rtol=1e-12)
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
