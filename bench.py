@@ -62,7 +62,7 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
     histories), then `steps` replays of the captured step, continuing the same
     run, timed with events on the library's stream.  Each captured solve issues
     a fixed number of PCG iteration kernels, sized from the second half of the
-    warm-up; a solve that needs more continues in one cooperative launch.  If a
+    warm-up; a solve that needs more continues in one persistent launch.  If a
     solve still fails (maxit), the measurement is repeated with twice the
     budget."""
     import numpy as np
@@ -78,7 +78,7 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
         its = ec.info_array(info)["iters"]
         if budgets is None:
             # typical, not worst-case, counts: a longer solve (cold start, the
-            # end of the ramp) is finished by the cooperative tail kernel
+            # end of the ramp) is finished by the persistent tail kernel
             h = warmup // 2
             budgets = [max(1, int(np.percentile(its[2 * h + q::2], 75)) + 2) for q in (0, 1)]
         G.counters_reset()

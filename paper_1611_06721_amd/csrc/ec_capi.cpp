@@ -81,7 +81,7 @@ struct ec_problem {
     CgCtl *cg_d = nullptr;
     double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr;
     unsigned *bar = nullptr;     // grid-barrier counters of the PCG tail kernel
-    int tail_blocks = 0;         // cooperative tail grid (0: no tail available)
+    int tail_blocks = 0;         // persistent tail grid (0: no tail available)
     // 2.5D PCG iteration (large grids): column width, planes per block, tile
     // counts and its grid; used while cg_blocks == grid25
     int t25 = 0, kb25 = 0, nti25 = 0, ntj25 = 0, ntk25 = 0, grid25 = 0, node_blocks = 0;
@@ -677,12 +677,12 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
         if (want > 0) budget = std::min(budget, want);
         for (int i = 0; i < budget; ++i) cg_iter<T>(a, i, st);
         // rare long solves (cold start, a sudden change of the source) finish
-        // in one cooperative launch instead of failing at the budget
+        // in one persistent launch instead of failing at the budget
         if constexpr (std::is_same<T, double>::value) {
             if (tail) {
                 hipError_t e = cg_tail<double>(a, budget, h->tail_blocks, st);
                 if (e != hipSuccess)
-                    return fail(h, EC_ERR_HIP, "cooperative tail launch: %s", hipGetErrorString(e));
+                    return fail(h, EC_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
             }
         }
         *n_issued = budget;

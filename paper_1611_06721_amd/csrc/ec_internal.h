@@ -147,7 +147,7 @@ struct CgArgs {
 };
 
 // grid barrier: counter words kBarStride apart (separate 128-byte lines);
-// bounded wait of the cooperative tail kernel
+// bounded wait of the persistent tail kernel
 constexpr int kBarStride = 32;
 constexpr long kSpinLimit = 1L << 22;
 
@@ -162,10 +162,11 @@ void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, i
                    int it, hipStream_t st);
 // *flag (device int) = 1 if every solve of tab[0..n) finished before iteration it
 void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t st);
-// blocks of the cooperative tail (one per CU, a multiple of 8; 0 on failure)
+// blocks of the persistent tail (at most two per CU, all resident at once, a
+// multiple of 8; 0 on failure)
 template <typename T>
 int cg_tail_blocks();
-// iterations it0.. of an unfinished solve in one cooperative launch
+// iterations it0.. of an unfinished solve in one persistent launch
 template <typename T>
 hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st);
 

@@ -330,7 +330,7 @@ def test_trajectory_nonlinear16(ec, oracle_mod):
 def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
     """Captured steps replayed after eager warm-up steps: with iteration
     budgets that cover every solve the trajectory is bitwise the eager one;
-    with budgets far too small the cooperative tail finishes the solves (same
+    with budgets far too small the persistent tail finishes the solves (same
     iterates up to the order of the reductions); maxit still reports
     NOT_CONVERGED."""
     G1, O, wl = pair(ec, oracle_mod, name)
