@@ -24,6 +24,11 @@ namespace ec {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int K = kMaxWin;
 constexpr int KC = EC_MAX_WINDOW + 1;     // columns a basis can hold
+// threads of the tall-skinny kernels: 16 waves per block (four per SIMD)
+// hide the memory latency of these streaming passes; the grid stays at
+// kMdBlocks blocks, so the partial rows keep their count
+constexpr int kMdThreads = 1024;
+constexpr int kMdWaves = kMdThreads / 64;
 
 // ------------------------------------------------ small dense primitives
 // All threads of the block call these (uniform barriers); serial parts run
@@ -475,10 +480,10 @@ __device__ __forceinline__ void load4(const double *col, int64_t row, int64_t n,
     }
 }
 
-__global__ void __launch_bounds__(256) k_multidot(MdArgs a)
+__global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a)
 {
     if (a.active && !*a.active) return;
-    __shared__ double red[4][32][4];
+    __shared__ double red[kMdWaves][32][4];
     const int k = a.kp ? *a.kp : a.kfix;
     const int p = k + (a.a_extra ? 1 : 0);
     const int nb = a.nb;
@@ -500,7 +505,7 @@ __global__ void __launch_bounds__(256) k_multidot(MdArgs a)
     }
     dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     const int64_t n = a.n;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wv, nw = (int64_t)gridDim.x * 4;
+    const int64_t gw = (int64_t)blockIdx.x * kMdWaves + wv, nw = (int64_t)gridDim.x * kMdWaves;
     // two 16-row groups per iteration: every load of both groups is issued
     // before the matrix-core work that consumes them
     for (int64_t r0 = gw * 16; r0 < n; r0 += 2 * nw * 16) {
@@ -543,30 +548,31 @@ __global__ void __launch_bounds__(256) k_multidot(MdArgs a)
         }
     }
     __syncthreads();
+    // one thread per value sums the waves in a fixed order
     const int nvals = p * nb;
-    if (threadIdx.x == 0) {
-        for (int t = 0; t < nvals; ++t) {
-            const int i = t / nb, j = t - i * nb;
-            const double s = ((red[0][i][j] + red[1][i][j]) + red[2][i][j]) + red[3][i][j];
-            a.part[(int64_t)t * kMdBlocks + blockIdx.x] = s;     // value-major
-        }
+    for (int t = threadIdx.x; t < nvals; t += blockDim.x) {
+        const int i = t / nb, j = t - i * nb;
+        double s = red[0][i][j];
+#pragma unroll
+        for (int w = 1; w < kMdWaves; ++w) s += red[w][i][j];
+        a.part[(int64_t)t * kMdBlocks + blockIdx.x] = s;         // value-major
     }
 }
 
 void multidot(const MdArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks), dim3(kMdThreads), 0, st, a);
 }
 
 // ----------------------------------------------------- linear combinations
 // y1 = a1 v1 + sum_{i<k} cA_i A_i        (y1 may be column *slot of A)
 // y2 = a2 s2 v2 + sum_{i<k} cB_i B_i
 // partials: [0..k) A_i^T y1 (want_dots), then |y1|^2, |y2|^2, |s2 v2|^2
-__global__ void __launch_bounds__(256) k_lincomb(LcArgs a)
+__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs a)
 {
     if (a.active && !*a.active) return;
     __shared__ double sA[kMaxWin], sB[kMaxWin];
-    __shared__ double lds[kMaxWin + 3][4];
+    __shared__ double lds[kMaxWin + 3][kMdWaves];
     const int k = a.kp ? *a.kp : 0;
     if (threadIdx.x < kMaxWin) {
         sA[threadIdx.x] = (a.cA && (int)threadIdx.x < k) ? a.cA[threadIdx.x] : 0.0;
@@ -585,6 +591,7 @@ __global__ void __launch_bounds__(256) k_lincomb(LcArgs a)
     for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < a.n; row += stride) {
         double v = (a.v1 && a1 != 0.0) ? a1 * a.v1[row] : 0.0;
         double u = 0.0;
+#pragma unroll 4
         for (int i = 0; i < k; ++i) {
             v += sA[i] * a.A[(int64_t)i * a.ld + row];
             if (a.y2) u += sB[i] * a.B[(int64_t)i * a.ld + row];
@@ -625,25 +632,24 @@ __global__ void __launch_bounds__(256) k_lincomb(LcArgs a)
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double *P = a.part + blockIdx.x;                         // value-major
-        for (int i = 0; i < nv; ++i)
-            P[(int64_t)i * kMdBlocks] = ((lds[i][0] + lds[i][1]) + lds[i][2]) + lds[i][3];
-        for (int q = 0; q < 3; ++q)
-            P[(int64_t)(nv + q) * kMdBlocks] =
-                ((lds[kMaxWin + q][0] + lds[kMaxWin + q][1]) + lds[kMaxWin + q][2]) +
-                        lds[kMaxWin + q][3];
+    // one thread per value sums the waves in a fixed order (value-major)
+    for (int t = threadIdx.x; t < nv + 3; t += blockDim.x) {
+        const int q = t < nv ? t : kMaxWin + (t - nv);
+        double s = lds[q][0];
+#pragma unroll
+        for (int w = 1; w < kMdWaves; ++w) s += lds[q][w];
+        a.part[(int64_t)t * kMdBlocks + blockIdx.x] = s;
     }
 }
 
 void lincomb(const LcArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks), dim3(kMdThreads), 0, st, a);
 }
 
 // In-place rotation of the first rot_in columns of A (and B) into rot_k
 // columns: A'_j = sum_i rot[i][j] A_i.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kMdThreads)
     k_rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq)
 {
     if (!seq->rotate) return;
@@ -672,7 +678,7 @@ __global__ void __launch_bounds__(256)
 
 void rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rotate, dim3(kMdBlocks), dim3(256), 0, st, A, B, ld, n, seq);
+    hipLaunchKernelGGL(k_rotate, dim3(kMdBlocks), dim3(kMdThreads), 0, st, A, B, ld, n, seq);
 }
 
 // One block: reduce the partial rows of the preceding basis product, then
