@@ -361,7 +361,7 @@ static int64_t layout(ec_problem *h, int cap, char *base)
     h->part_cg = (double *)take(2 * 4 * (int64_t)kMaxBlocks * 8);
     h->part_md = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
     h->part_ref = (double *)take(2 * (int64_t)kMaxBlocks * 8);
-    h->bar = (unsigned *)take(9 * kBarStride * sizeof(unsigned));
+    h->bar = (unsigned *)take((int64_t)kBarWords * kBarStride * sizeof(unsigned));
     h->ld = ld;
     return off;
 }

@@ -139,16 +139,18 @@ struct CgArgs {
     const int *skip;         // device flag: nonzero -> kernels return at once
     int tiles;
     int blocks;
-    unsigned *bar;           // grid-barrier counters of the tail kernel (9 x kBarStride)
+    unsigned *bar;           // grid-barrier words of the tail kernel (kBarWords x kBarStride)
     // 2.5D iteration kernel (large grids): TI of the node column (0: the
     // node-parallel kernel), planes per block and the tile counts; the 2.5D
     // grid is `blocks`
     int t25, kb25, nti25, ntj25, ntk25;
 };
 
-// grid barrier: counter words kBarStride apart (separate 128-byte lines);
-// bounded wait of the persistent tail kernel
+// grid barrier of the persistent tail kernel: 8 release words, then one
+// arrival word per block, each kBarStride words apart (separate 128-byte
+// lines); bounded waits
 constexpr int kBarStride = 32;
+constexpr int kBarWords = 8 + kMaxBlocks;
 constexpr long kSpinLimit = 1L << 22;
 
 template <typename T>

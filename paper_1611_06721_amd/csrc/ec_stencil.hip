@@ -249,10 +249,11 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
             c0.status = EC_OK;
             c0.zero_x = zero_all;
             a.ctl[0] = c0;
-            if (a.bar)
-                for (int q = 0; q <= 8; ++q) a.bar[q * kBarStride] = 0u;
         }
     }
+    // arrival and release words of the tail kernel's barrier
+    if (blockIdx.x == 0 && a.bar)
+        for (int q = threadIdx.x; q < kBarWords; q += blockDim.x) a.bar[(int64_t)q * kBarStride] = 0u;
 }
 
 // State entering kernel i from the reduced partials t = (gamma, delta, rho,
@@ -597,32 +598,60 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Grid barrier of a launch whose blocks are all resident: blocks arrive
-// on one counter per group of eight (block b in group b % 8), the last of a
-// group bumps the top counter, every block waits for the top counter to
-// reach 8 * gen.  Agent-scope fences publish this block's stores (partials
-// and vectors, read by other blocks after the barrier).  The wait is bounded:
-// false if the spin limit was reached (never expected).
+// Grid barrier of a launch whose blocks are all resident.  Every block posts
+// its arrival (the generation) in a word of its own; the threads of block 0
+// watch all arrival words together, then post the generation to eight release
+// words, and block b watches word b % 8.  Polls are relaxed loads from
+// separate 128-byte lines (no shared counter that every block updates or
+// polls); an agent-scope release fence before the arrival and an acquire
+// fence after the release publish the vectors and partials the blocks wrote.
+// Every wait is bounded: false if the spin limit was reached (never
+// expected); block 0 then posts no release and the other blocks time out too.
 __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen)
 {
     __shared__ int s_ok;
+    unsigned *rel = bar, *arrive = bar + 8 * kBarStride;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned grp = blockIdx.x & 7, per = gridDim.x >> 3;
-        __threadfence();
-        const unsigned old = atomicAdd(bar + grp * kBarStride, 1u);
-        if (old + 1 == gen * per) atomicAdd(bar + 8 * kBarStride, 1u);
-        int ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(arrive + (int64_t)blockIdx.x * kBarStride, gen, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    if (blockIdx.x == 0) {
         long spins = 0;
-        while (__hip_atomic_load(bar + 8 * kBarStride, __ATOMIC_ACQUIRE,
-                                 __HIP_MEMORY_SCOPE_AGENT) < 8u * gen) {
+        for (;;) {
+            int mine = 1;
+            for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
+                if (__hip_atomic_load(arrive + (int64_t)q * kBarStride, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) < gen)
+                    mine = 0;
+            if (__syncthreads_and(mine)) break;
             if (++spins > kSpinLimit) {
                 ok = 0;
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
         }
-        __threadfence();
+        if (ok && threadIdx.x < 8) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(rel + threadIdx.x * kBarStride, gen, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (ok) {
+            const unsigned *w = rel + (blockIdx.x & 7) * kBarStride;
+            long spins = 0;
+            while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+                if (++spins > kSpinLimit) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
