@@ -168,32 +168,35 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
         __syncthreads();
         bool good = k > 0;
         if (good) good = chol_solve(sq->H, Ls, ys, gs, k);
+        // entries are independent: one per thread (no chain of dependent
+        // global loads and stores on thread 0)
+        for (int i = tid; i < K; i += nt) {
+            const double c = (good && i < k) ? ys[i] * sq->s[i] : 0.0;
+            sq->cA[i] = c;
+            sq->cB[i] = -c;
+        }
         if (tid == 0) {
             sq->flags = (k > 0 && !good) ? 1 : 0;
             sq->zero_start = good ? 0 : 1;
             sq->a1 = 0.0;
             sq->a2 = 1.0;
             sq->ncol_md = good ? k : 0;
-            for (int i = 0; i < K; ++i) {
-                const double c = (good && i < k) ? ys[i] * sq->s[i] : 0.0;
-                sq->cA[i] = c;
-                sq->cB[i] = -c;
-            }
             sq->active = 1;
         }
         break;
     }
     case OP_SPE_PUSH1: {
         // c1 = q^T x; w = x - q c1
+        for (int i = tid; i < K; i += nt) {
+            const double si = i < k ? sq->s[i] : 0.0;
+            const double c1 = si * (i < k ? val[i] : 0.0);
+            sq->c1[i] = c1;
+            sq->cA[i] = -c1 * si;
+        }
         if (tid == 0) {
             const double xx = val[k];
             sq->xnorm = sqrt(xx);
             sq->active = (xx > 0.0 && xx <= 1e300) ? 1 : 0;
-            for (int i = 0; i < K; ++i) {
-                const double c1 = i < k ? sq->s[i] * val[i] : 0.0;
-                sq->c1[i] = c1;
-                sq->cA[i] = i < k ? -c1 * sq->s[i] : 0.0;
-            }
             sq->a1 = 1.0;
             sq->slot_new = k;
             sq->ncol_md = k;
@@ -204,14 +207,13 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
     }
     case OP_SPE_PUSH2: {
         // second pass: c2 = q^T w; x2 = w - q c2
-        if (tid == 0) {
-            for (int i = 0; i < K; ++i) {
-                const double c2 = i < k ? sq->s[i] * val[i] : 0.0;
-                sq->c2[i] = c2;
-                sq->cA[i] = i < k ? -c2 * sq->s[i] : 0.0;
-            }
-            sq->a1 = 1.0;
+        for (int i = tid; i < K; i += nt) {
+            const double si = i < k ? sq->s[i] : 0.0;
+            const double c2 = si * (i < k ? val[i] : 0.0);
+            sq->c2[i] = c2;
+            sq->cA[i] = -c2 * si;
         }
+        if (tid == 0) sq->a1 = 1.0;
         break;
     }
     case OP_SPE_PUSH3: {
@@ -230,18 +232,24 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
     }
     case OP_SPE_PUSH4: {
         // new row/column of H = q^T K q and of the window coordinates R
+        const int acc = sq->accept;
+        if (acc) {
+            const double sk = sq->s[k];
+            for (int i = tid; i <= k; i += nt) {
+                const double h = sq->s[i] * sk * val[i];
+                sq->H[i * K + k] = h;
+                sq->H[k * K + i] = h;
+            }
+            for (int i = tid; i < k; i += nt) {
+                sq->R[i * K + k] = sq->c1[i] + sq->c2[i];
+                sq->R[k * K + i] = 0.0;
+            }
+        }
+        __syncthreads();
         if (tid == 0) {
             sq->rotate = 0;
-            if (sq->accept) {
-                const double sk = sq->s[k];
-                for (int i = 0; i <= k; ++i) {
-                    const double h = sq->s[i] * sk * val[i];
-                    sq->H[i * K + k] = h;
-                    sq->H[k * K + i] = h;
-                }
-                for (int i = 0; i < k; ++i) sq->R[i * K + k] = sq->c1[i] + sq->c2[i];
+            if (acc) {
                 sq->R[k * K + k] = sq->rho;
-                for (int j = 0; j < k; ++j) sq->R[k * K + j] = 0.0;
                 sq->k = k + 1;
                 sq->w = sq->w + 1;
             }
@@ -298,8 +306,8 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
             sq->rot[t] = (i < n && j < n - 1) ? Ms[j * K + i] * sq->s[i] : 0.0;
         }
         __syncthreads();
+        for (int i = tid; i <= K; i += nt) sq->s[i] = 1.0;
         if (tid == 0) {
-            for (int i = 0; i <= K; ++i) sq->s[i] = 1.0;
             sq->rot_in = n;
             sq->rot_k = n - 1;
             sq->k = n - 1;
