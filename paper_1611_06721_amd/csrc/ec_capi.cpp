@@ -627,15 +627,13 @@ static void seq_push(ec_problem *h, int seq, int method, const double *x)
     l.want_dots = 0;
     lincomb(l, st);
     dense(h, seq, OP_SPE_PUSH3);
-    spmv_slot(h->g, h->t2, h->t3, KQ, Q, &sd->slot_new, h->ld, &sd->active, st);
-    // new column of Q^T (K_n + eta D^T D) Q: the grad-div term keeps the
-    // projection from amplifying the gradient part of the window
+    // the new column and its K_n product into their slots, and in the same
+    // pass (K_n + eta D^T D) t2 for the new column of Q^T (K_n + eta D^T D) Q:
+    // the grad-div term keeps the projection from amplifying the gradient
+    // part of the window
     const double eta = h->seq_eta[seq];
-    const double *kq = h->t3;
-    if (eta > 0.0) {
-        graddiv(h->g, h->t2, h->t3, h->t4, eta, &sd->active, st);
-        kq = h->t4;
-    }
+    spmv_slot_penal(h->g, h->t2, h->t4, KQ, Q, &sd->slot_new, h->ld, eta, &sd->active, st);
+    const double *kq = h->t4;
     MdArgs m2 = md_args(h);
     m2.A = Q;
     m2.kp = &sd->ncol_md;

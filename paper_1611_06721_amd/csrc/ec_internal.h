@@ -98,11 +98,11 @@ void spmv(const Geo &g, const double *x, double *y, const int lo[3], const int h
 // ycopy + (*slot)*ld and x to xcopy + (*slot)*ld; skipped when *active == 0
 void spmv_slot(const Geo &g, const double *x, double *y, double *ycopy, double *xcopy,
                const int *slot, int64_t ld, const int *active, hipStream_t st);
+// ycopy/xcopy columns as spmv_slot, and ypen = K_n x + eta D^T D x on
+// nonconducting edges (= K_n x for eta = 0); skipped when *active == 0
+void spmv_slot_penal(const Geo &g, const double *x, double *ypen, double *ycopy, double *xcopy,
+                     const int *slot, int64_t ld, double eta, const int *active, hipStream_t st);
 void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st);
-// y = kx + eta D^T D x on nonconducting edges (D: divergence at free nodes);
-// skipped when *active == 0
-void graddiv(const Geo &g, const double *x, const double *kx, double *y, double eta,
-             const int *active, hipStream_t st);
 
 // PCG start modes
 enum { START_ZERO = 0, START_X = 1, START_R = 2, START_DEV = 3, START_R2 = 4 };

@@ -24,14 +24,35 @@
 
 namespace ec {
 
+// ------------------------------------------------------- grad-div penalty
+// G^T x at node (i,j,k) when the node is free (interior, and no conducting
+// edge ends there), else 0.  G phi puts phi(head) - phi(tail) on an edge.
+__device__ __forceinline__ double free_div(const Geo &g, const double *__restrict__ x, int i,
+                                           int j, int k)
+{
+    if (i <= 0 || i >= g.nx || j <= 0 || j >= g.ny || k <= 0 || k >= g.nz) return 0.0;
+    const int64_t oj = g.px, ok = (int64_t)g.px * g.py;
+    const int64_t n = k * ok + j * oj + i;
+    if (edge_cls(g, 0, i, j, k, n) == 1 || edge_cls(g, 0, i - 1, j, k, n - 1) == 1 ||
+        edge_cls(g, 1, i, j, k, n) == 1 || edge_cls(g, 1, i, j - 1, k, n - oj) == 1 ||
+        edge_cls(g, 2, i, j, k, n) == 1 || edge_cls(g, 2, i, j, k - 1, n - ok) == 1)
+        return 0.0;
+    const int64_t S = g.S;
+    return (x[n - 1] - x[n]) + (x[S + n - oj] - x[S + n]) + (x[2 * S + n - ok] - x[2 * S + n]);
+}
+
 // ------------------------------------------------------------- SpMV kernel
 // Blocks are mapped XCD-contiguously (block b runs on XCD b % 8): each XCD
 // sweeps one slab, so the k +- 1 planes of the stencil stay in its own L2.
+// y (if given) = K_n x; ycopy/xcopy (if given) receive K_n x and x at column
+// *slot; ypen (if given, FP64) = K_n x + eta D^T D x on nonconducting edges,
+// the same value the grad-div kernel forms from K_n x.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_spmv(Geo g, const T *__restrict__ x, T *__restrict__ y, int lo0, int lo1, int lo2,
            int ex, int ey, int ez, int tiles, int tpx, T *__restrict__ ycopy,
-           T *__restrict__ xcopy, const int *slot, int64_t ld, const int *active)
+           T *__restrict__ xcopy, const int *slot, int64_t ld, const int *active,
+           T *__restrict__ ypen, double eta)
 {
     if (active && !*active) return;
     const int b = blockIdx.x, tile = (b & 7) * tpx + (b >> 3);
@@ -52,27 +73,45 @@ __global__ void __launch_bounds__(256)
     const int64_t n = ((int64_t)k * g.py + j) * g.px + i;
     T q[3];
     curlcurl_node<T>(g, n, [&](int, int64_t a) { return x[a]; }, q[0], q[1], q[2]);
+    double d0 = 0.0, dh[3] = {0.0, 0.0, 0.0};
+    if constexpr (std::is_same<T, double>::value) {
+        if (ypen && eta > 0.0) {
+            d0 = free_div(g, x, i, j, k);
+            dh[0] = free_div(g, x, i + 1, j, k);
+            dh[1] = free_div(g, x, i, j + 1, k);
+            dh[2] = free_div(g, x, i, j, k + 1);
+        }
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int64_t ix = (int64_t)c * g.S + n;
-        const T v = edge_cls(g, c, i, j, k, n) == 2 ? q[c] : (T)0;
-        y[ix] = v;
+        const bool nc = edge_cls(g, c, i, j, k, n) == 2;
+        const T v = nc ? q[c] : (T)0;
+        if (y) y[ix] = v;
         if (ycopy) ycopy[ix] = v;
         if (xcopy) xcopy[ix] = x[ix];
+        if constexpr (std::is_same<T, double>::value) {
+            if (ypen) {
+                double vp = v;
+                if (nc && eta > 0.0) vp += eta * (dh[c] - d0);
+                ypen[ix] = vp;
+            }
+        }
     }
 }
 
 template <typename T>
 static void spmv_launch_box(const Geo &g, const T *x, T *y, const int lo[3], const int ext[3],
                             hipStream_t st, T *ycopy, T *xcopy, const int *slot, int64_t ld,
-                            const int *active)
+                            const int *active, T *ypen = nullptr, double eta = 0.0)
 {
     const int64_t cnt = (int64_t)ext[0] * ext[1] * ext[2];
     if (cnt <= 0) return;
     const int tiles = (int)((cnt + kTile - 1) / kTile);
     const int tpx = (tiles + 7) / 8;
     hipLaunchKernelGGL(k_spmv<T>, dim3(8 * tpx), dim3(kTile), 0, st, g, x, y, lo[0], lo[1],
-                       lo[2], ext[0], ext[1], ext[2], tiles, tpx, ycopy, xcopy, slot, ld, active);
+                       lo[2], ext[0], ext[1], ext[2], tiles, tpx, ycopy, xcopy, slot, ld, active,
+                       ypen, eta);
 }
 
 void spmv(const Geo &g, const double *x, double *y, const int lo[3], const int hi[3],
@@ -89,58 +128,17 @@ void spmv_slot(const Geo &g, const double *x, double *y, double *ycopy, double *
     spmv_launch_box<double>(g, x, y, lo, ext, st, ycopy, xcopy, slot, ld, active);
 }
 
+void spmv_slot_penal(const Geo &g, const double *x, double *ypen, double *ycopy, double *xcopy,
+                     const int *slot, int64_t ld, double eta, const int *active, hipStream_t st)
+{
+    const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
+    spmv_launch_box<double>(g, x, nullptr, lo, ext, st, ycopy, xcopy, slot, ld, active, ypen, eta);
+}
+
 void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st)
 {
     const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
     spmv_launch_box<float>(g, x, y, lo, ext, st, nullptr, nullptr, nullptr, 0, nullptr);
-}
-
-// ------------------------------------------------------- grad-div penalty
-// G^T x at node (i,j,k) when the node is free (interior, and no conducting
-// edge ends there), else 0.  G phi puts phi(head) - phi(tail) on an edge.
-__device__ __forceinline__ double free_div(const Geo &g, const double *__restrict__ x, int i,
-                                           int j, int k)
-{
-    if (i <= 0 || i >= g.nx || j <= 0 || j >= g.ny || k <= 0 || k >= g.nz) return 0.0;
-    const int64_t oj = g.px, ok = (int64_t)g.px * g.py;
-    const int64_t n = k * ok + j * oj + i;
-    if (edge_cls(g, 0, i, j, k, n) == 1 || edge_cls(g, 0, i - 1, j, k, n - 1) == 1 ||
-        edge_cls(g, 1, i, j, k, n) == 1 || edge_cls(g, 1, i, j - 1, k, n - oj) == 1 ||
-        edge_cls(g, 2, i, j, k, n) == 1 || edge_cls(g, 2, i, j, k - 1, n - ok) == 1)
-        return 0.0;
-    const int64_t S = g.S;
-    return (x[n - 1] - x[n]) + (x[S + n - oj] - x[S + n]) + (x[2 * S + n - ok] - x[2 * S + n]);
-}
-
-// y = kx + eta D^T D x on nonconducting edges (kx elsewhere), D the divergence
-// at the free nodes: the grad-div term that makes the SPE projection see the
-// gradient (null-space) part of its basis.  One thread per node.
-__global__ void __launch_bounds__(256)
-    k_graddiv(Geo g, const double *__restrict__ x, const double *__restrict__ kx,
-              double *__restrict__ y, double eta, const int *active)
-{
-    if (active && !*active) return;
-    const int64_t n = (int64_t)blockIdx.x * kTile + threadIdx.x;
-    if (n >= g.S) return;
-    int i, j, k;
-    decode(g, n, i, j, k);
-    const double d0 = free_div(g, x, i, j, k);
-    const double dh[3] = {free_div(g, x, i + 1, j, k), free_div(g, x, i, j + 1, k),
-                          free_div(g, x, i, j, k + 1)};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int64_t ix = (int64_t)c * g.S + n;
-        double v = kx[ix];
-        if (edge_cls(g, c, i, j, k, n) == 2) v += eta * (dh[c] - d0);
-        y[ix] = v;
-    }
-}
-
-void graddiv(const Geo &g, const double *x, const double *kx, double *y, double eta,
-             const int *active, hipStream_t st)
-{
-    const int blocks = (int)((g.S + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_graddiv, dim3(blocks), dim3(kTile), 0, st, g, x, kx, y, eta, active);
 }
 
 // ------------------------------------------------------------------- CG
@@ -299,29 +297,83 @@ __device__ __forceinline__ CgCtl cg_state(const CgCtl &prev, const double (&t)[4
 // previous iteration (every block, same order), decide, then update x, p, s,
 // r, w and leave this iteration's partials.  Returns true (uniformly in every
 // block) when the solve was already finished and nothing was updated.
+// This thread's share of the nb block partials of iteration it (strided
+// loads, summed in the same order as reduce_partials).
+__device__ __forceinline__ void part_load(const double *P, int nb, double (&t)[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = 0.0;
+    // four strides' loads in flight before any is summed (one round trip for
+    // up to 4 x blockDim blocks)
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * (int)blockDim.x) {
+        double v[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * (int)blockDim.x;
+            if (b < nb) {
+                const double2 *p2 = reinterpret_cast<const double2 *>(P + (int64_t)b * 4);
+                const double2 lo = p2[0], hi = p2[1];
+                v[u][0] = lo.x; v[u][1] = lo.y; v[u][2] = hi.x; v[u][3] = hi.y;
+            } else {
+                v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] += v[u][q];
+    }
+}
+
+// Block-reduce the thread shares t, decide the state entering iteration it;
+// block bid 0 passes the record on.  True (uniformly) when the solve is
+// finished.
+template <typename T>
+__device__ __forceinline__ bool cg_decide(const CgArgs<T> &a, int it, double (&t)[4], CgCtl &s_c,
+                                          double &s_beta, int bid)
+{
+    block_sum<4>(t);
+    if (threadIdx.x == 0) {
+        double beta;
+        const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
+        s_c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
+        s_beta = beta;
+        if (bid == 0) {
+            CgCtl o = s_c;
+            if (!o.done) o.it = it + 1;   // iterations completed after this one
+            a.ctl[(it + 1) & 1] = o;
+        }
+    }
+    __syncthreads();
+    return s_c.done != 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void cg_update(const CgArgs<T> &a, int it, const CgCtl &s_c,
+                                          double s_beta, int bid, int nb);
+
+// One PCG iteration `it` by the whole grid: reduce the nprev partials of the
+// previous iteration (every block, same order), decide, then update x, p, s,
+// r, w and leave this iteration's partials.  Returns true (uniformly in every
+// block) when the solve was already finished and nothing was updated.
 template <typename T>
 __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int nprev, CgCtl &s_c,
                                              double &s_beta, int bid, int nb)
 {
-    const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;
+    double t[4];
+    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, nprev, t);
+    if (cg_decide<T>(a, it, t, s_c, s_beta, bid)) return true;
+    cg_update<T>(a, it, s_c, s_beta, bid, nb);
+    return false;
+}
+
+// The update of iteration it after the decision: x, p, s, r, w of the
+// block's tiles and this iteration's partials.
+template <typename T>
+__device__ __forceinline__ void cg_update(const CgArgs<T> &a, int it, const CgCtl &s_c,
+                                          double s_beta, int bid, int nb)
+{
     double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
-    {
-        double t[4];
-        sum_part(Pin, nprev, t);
-        if (threadIdx.x == 0) {
-            double beta;
-            const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
-            s_c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
-            s_beta = beta;
-            if (bid == 0) {
-                CgCtl o = s_c;
-                if (!o.done) o.it = it + 1;   // iterations completed after this one
-                a.ctl[(it + 1) & 1] = o;
-            }
-        }
-        __syncthreads();
-    }
-    if (s_c.done) return true;
     const Geo &g = a.g;
     const int64_t S = g.S;
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
@@ -369,22 +421,24 @@ __device__ __forceinline__ bool cg_iteration(const CgArgs<T> &a, int it, int npr
     block_sum<4>(v);
     if (threadIdx.x == 0)
         for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
-    return false;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
 {
     if (a.skip && *a.skip) return;
-    // a finished solve: pass the record on and leave before any reduction
-    // (graph replays issue a fixed number of these kernels)
+    // a finished solve: pass the record on and leave before loading the
+    // partials (graph replays issue a fixed number of these kernels)
     if (a.ctl[it & 1].done) {
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
         return;
     }
+    double t[4];
+    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, gridDim.x, t);
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
-    cg_iteration<T>(a, it, gridDim.x, s_c, s_beta, blockIdx.x, gridDim.x);
+    if (cg_decide<T>(a, it, t, s_c, s_beta, blockIdx.x)) return;
+    cg_update<T>(a, it, s_c, s_beta, blockIdx.x, gridDim.x);
 }
 
 // One iteration of every solve of a batch in one launch: block b serves
@@ -402,9 +456,12 @@ __global__ void __launch_bounds__(256)
         if (bid == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
         return;
     }
+    double t[4];
+    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, a.blocks, t);
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
-    cg_iteration<double>(a, it, a.blocks, s_c, s_beta, bid, a.blocks);
+    if (cg_decide<double>(a, it, t, s_c, s_beta, bid)) return;
+    cg_update<double>(a, it, s_c, s_beta, bid, a.blocks);
 }
 
 // *flag = 1 if every solve of the batch has finished before iteration it
@@ -430,31 +487,6 @@ void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t
     hipLaunchKernelGGL(k_batch_done, dim3(1), dim3(256), 0, st, tab, n, it, flag);
 }
 
-// Prologue of an iteration kernel: reduce the nprev partials of the previous
-// iteration (same order in every block), decide; block bid 0 passes the
-// record on.  True when the solve was already finished.
-template <typename T>
-__device__ __forceinline__ bool cg_begin(const CgArgs<T> &a, int it, int nprev, CgCtl &s_c,
-                                         double &s_beta, int bid)
-{
-    const double *Pin = a.part + (int64_t)(it & 1) * 4 * kMaxBlocks;
-    double t[4];
-    sum_part(Pin, nprev, t);
-    if (threadIdx.x == 0) {
-        double beta;
-        const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
-        s_c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
-        s_beta = beta;
-        if (bid == 0) {
-            CgCtl o = s_c;
-            if (!o.done) o.it = it + 1;
-            a.ctl[(it + 1) & 1] = o;
-        }
-    }
-    __syncthreads();
-    return s_c.done != 0;
-}
-
 // One PCG iteration for large grids (2.5D blocking).  Block b owns the node
 // column [i0, i0+TI) x [j0, j0+TJ) (TI*TJ = 256 threads, one node each) and
 // the planes [k0, k0+kb).  The transformed input
@@ -477,7 +509,11 @@ __global__ void __launch_bounds__(256)
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
         return;
     }
-    if (cg_begin<T>(a, it, gridDim.x, s_c, s_beta, blockIdx.x)) return;
+    {
+        double t[4];
+        part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, gridDim.x, t);
+        if (cg_decide<T>(a, it, t, s_c, s_beta, blockIdx.x)) return;
+    }
     const Geo &g = a.g;
     const int64_t S = g.S, oj = g.px, ok = (int64_t)g.px * g.py;
     const T dd[3] = {(T)g.dinv[0], (T)g.dinv[1], (T)g.dinv[2]};
