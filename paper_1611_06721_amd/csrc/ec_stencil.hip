@@ -531,52 +531,64 @@ __global__ void __launch_bounds__(256)
         const int lx = threadIdx.x % TI, ly = threadIdx.x / TI;
         const int i = i0 + lx, j = j0 + ly;
         const bool own = i < g.nx && j < g.ny;
-        // t of plane kk into ring slot kk % 3 (zero outside the grid)
-        auto load_plane = [&](int kk) {
-            T(*dst)[LP] = lt[((kk % 3) + 3) % 3];
-            for (int q = threadIdx.x; q < LP; q += 256) {
-                const int li = q % LI, lj = q / LI;
-                const int ii = i0 - 1 + li, jj = j0 - 1 + lj;
-                T t0 = (T)0, t1 = (T)0, t2 = (T)0;
-                if (kk >= 0 && kk <= g.nz && ii >= 0 && ii < g.px && jj >= 0 && jj < g.py) {
-                    const int64_t n = kk * ok + (int64_t)jj * oj + ii;
-                    T tt[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const int64_t ix = c * S + n;
-                        const T u = first ? wc[ix] : wc[ix] + tb * sp[ix];
-                        tt[c] = dd[c] * (rc[ix] - ta * u);
-                    }
-                    t0 = tt[0]; t1 = tt[1]; t2 = tt[2];
-                }
-                dst[0][q] = t0;
-                dst[1][q] = t1;
-                dst[2][q] = t2;
-            }
-        };
-        load_plane(k0 - 1);
-        load_plane(k0);
         const int lc = (ly + 1) * LI + (lx + 1);
-        const T wx = (T)g.wx, wy = (T)g.wy, wz = (T)g.wz;
-        for (int k = k0; k < k1; ++k) {
-            // the node's own values of plane k first: their loads overlap the
-            // halo loads of plane k + 1 (neither waits for the barrier)
-            const int64_t n = k * ok + (int64_t)j * oj + i;
-            T orv[3] = {(T)0, (T)0, (T)0}, owv[3] = {(T)0, (T)0, (T)0};
-            T osp[3] = {(T)0, (T)0, (T)0}, opv[3] = {(T)0, (T)0, (T)0};
-            if (own) {
+        // r and u = w + beta s at node (ii, jj, kk) (zero outside the grid)
+        auto load_ru = [&](int kk, int ii, int jj, T(&rv)[3], T(&uv)[3]) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rv[c] = uv[c] = (T)0;
+            if (kk >= 0 && kk <= g.nz && ii >= 0 && ii < g.px && jj >= 0 && jj < g.py) {
+                const int64_t n = kk * ok + (int64_t)jj * oj + ii;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int64_t ix = c * S + n;
-                    orv[c] = rc[ix];
-                    owv[c] = wc[ix];
-                    if (!first) {
-                        osp[c] = sp[ix];
-                        opv[c] = a.p[ix];
-                    }
+                    rv[c] = rc[ix];
+                    uv[c] = first ? wc[ix] : wc[ix] + tb * sp[ix];
                 }
             }
-            load_plane(k + 1);
+        };
+        // t of plane kk into ring slot kk % 3.  Each thread loads its own
+        // position and keeps that node's r and u for the update of plane kk
+        // (no second load); the 2 LI + 2 TJ halo positions go to the first
+        // threads.
+        constexpr int NH = 2 * LI + 2 * TJ;
+        static_assert(NH <= 256, "halo positions exceed the block");
+        auto load_plane = [&](int kk, T(&rv)[3], T(&uv)[3]) {
+            T(*dst)[LP] = lt[((kk % 3) + 3) % 3];
+            load_ru(kk, i, j, rv, uv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[c][lc] = dd[c] * (rv[c] - ta * uv[c]);
+            if (threadIdx.x < NH) {
+                const int h = threadIdx.x;
+                int li, lj;
+                if (h < LI) {
+                    li = h; lj = 0;
+                } else if (h < 2 * LI) {
+                    li = h - LI; lj = LJ - 1;
+                } else if (h < 2 * LI + TJ) {
+                    li = 0; lj = 1 + (h - 2 * LI);
+                } else {
+                    li = LI - 1; lj = 1 + (h - 2 * LI - TJ);
+                }
+                T hr[3], hu[3];
+                load_ru(kk, i0 - 1 + li, j0 - 1 + lj, hr, hu);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dst[c][lj * LI + li] = dd[c] * (hr[c] - ta * hu[c]);
+            }
+        };
+        T cr[3], cu[3], nr[3], nu[3];
+        load_plane(k0 - 1, nr, nu);
+        load_plane(k0, cr, cu);
+        const T wx = (T)g.wx, wy = (T)g.wy, wz = (T)g.wz;
+        for (int k = k0; k < k1; ++k) {
+            // the node's p of plane k first: its loads overlap those of
+            // plane k + 1 (neither waits for the barrier)
+            const int64_t n = k * ok + (int64_t)j * oj + i;
+            T opv[3] = {(T)0, (T)0, (T)0};
+            if (own && !first) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) opv[c] = a.p[c * S + n];
+            }
+            load_plane(k + 1, nr, nu);
             __syncthreads();
             if (own) {
                 const T(*pm)[LP] = lt[((k - 1) % 3 + 3) % 3];
@@ -608,8 +620,7 @@ __global__ void __launch_bounds__(256)
                 for (int c = 0; c < 3; ++c) {
                     const int64_t ix = c * S + n;
                     const T d = dd[c];
-                    const T rv = orv[c], wv = owv[c];
-                    const T si = first ? wv : wv + tb * osp[c];
+                    const T rv = cr[c], si = cu[c];
                     const T pi = first ? d * rv : d * rv + tb * opv[c];
                     a.x[ix] += ta * pi;
                     a.p[ix] = pi;
@@ -625,6 +636,11 @@ __global__ void __launch_bounds__(256)
                 }
             }
             __syncthreads();           // the next load overwrites plane k - 1
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cr[c] = nr[c];
+                cu[c] = nu[c];
+            }
         }
     }
     block_sum<4>(v);
