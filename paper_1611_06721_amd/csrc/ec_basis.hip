@@ -488,8 +488,11 @@ __device__ __forceinline__ void load4(const double *col, int64_t row, int64_t n,
     }
 }
 
-__global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a)
+// Block row blockIdx.y serves argument set a0 or a1 (independent sequences
+// in one launch); each set sees exactly the single-set grid.
+__global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a0, MdArgs a1)
 {
+    const MdArgs a = blockIdx.y ? a1 : a0;
     if (a.active && !*a.active) return;
     __shared__ double red[kMdWaves][32][4];
     const int k = a.kp ? *a.kp : a.kfix;
@@ -567,17 +570,19 @@ __global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a)
     }
 }
 
-void multidot(const MdArgs &a, hipStream_t st)
+void multidot(const MdArgs &a, hipStream_t st, const MdArgs *a1)
 {
-    hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks), dim3(kMdThreads), 0, st, a);
+    hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st, a,
+                       a1 ? *a1 : a);
 }
 
 // ----------------------------------------------------- linear combinations
 // y1 = a1 v1 + sum_{i<k} cA_i A_i        (y1 may be column *slot of A)
 // y2 = a2 s2 v2 + sum_{i<k} cB_i B_i
 // partials: [0..k) A_i^T y1 (want_dots), then |y1|^2, |y2|^2, |s2 v2|^2
-__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs a)
+__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs set0, LcArgs set1)
 {
+    const LcArgs &a = blockIdx.y ? set1 : set0;
     if (a.active && !*a.active) return;
     __shared__ double sA[kMaxWin], sB[kMaxWin];
     __shared__ double lds[kMaxWin + 3][kMdWaves];
@@ -650,16 +655,20 @@ __global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs a)
     }
 }
 
-void lincomb(const LcArgs &a, hipStream_t st)
+void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1)
 {
-    hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks), dim3(kMdThreads), 0, st, a);
+    hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st, a,
+                       a1 ? *a1 : a);
 }
 
 // In-place rotation of the first rot_in columns of A (and B) into rot_k
 // columns: A'_j = sum_i rot[i][j] A_i.
 __global__ void __launch_bounds__(kMdThreads)
-    k_rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq)
+    k_rotate(RotArgs r0, RotArgs r1, int64_t ld, int64_t n)
 {
+    const RotArgs &r = blockIdx.y ? r1 : r0;
+    double *A = r.A, *B = r.B;
+    const SeqDev *seq = r.seq;
     if (!seq->rotate) return;
     __shared__ double R[K * K];
     const int kin = seq->rot_in, kout = seq->rot_k;
@@ -684,16 +693,20 @@ __global__ void __launch_bounds__(kMdThreads)
     }
 }
 
-void rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq, hipStream_t st)
+void rotate(const RotArgs &r, int64_t ld, int64_t n, hipStream_t st, const RotArgs *r1)
 {
-    hipLaunchKernelGGL(k_rotate, dim3(kMdBlocks), dim3(kMdThreads), 0, st, A, B, ld, n, seq);
+    hipLaunchKernelGGL(k_rotate, dim3(kMdBlocks, r1 ? 2 : 1), dim3(kMdThreads), 0, st, r,
+                       r1 ? *r1 : r, ld, n);
 }
 
-// One block: reduce the partial rows of the preceding basis product, then
-// run the dense step `op` of the sequence.
-__global__ void __launch_bounds__(256)
-    k_small(SeqDev *sq, int op, const double *part, int nvals, double tol, ec_solve_info *info)
+// One block per argument set (blockIdx.y): reduce the partial rows of the
+// preceding basis product, then run the dense step `op` of the sequence.
+__global__ void __launch_bounds__(256) k_small(SmallArgs s0, SmallArgs s1)
 {
+    const SmallArgs &sa = blockIdx.y ? s1 : s0;
+    SeqDev *sq = sa.seq;
+    const int op = sa.op, nvals = sa.nvals;
+    const double *part = sa.part;
     __shared__ double val[kMdStride];
     // exactly the values the producing product kernel wrote (state before the op)
     int nv = nvals;
@@ -710,13 +723,12 @@ __global__ void __launch_bounds__(256)
     nv = nv < 0 ? 0 : (nv > nvals ? nvals : nv);
     if (part) reduce_rows(part, nv, val);
     __syncthreads();
-    small_op(sq, op, val, tol, info);
+    small_op(sq, op, val, sa.tol, sa.info);
 }
 
-void small(SeqDev *seq, int op, const double *part, int nvals, double tol, ec_solve_info *info,
-           hipStream_t st)
+void small(const SmallArgs &a, hipStream_t st, const SmallArgs *a1)
 {
-    hipLaunchKernelGGL(k_small, dim3(1), dim3(256), 0, st, seq, op, part, nvals, tol, info);
+    hipLaunchKernelGGL(k_small, dim3(1, a1 ? 2 : 1), dim3(256), 0, st, a, a1 ? *a1 : a);
 }
 
 // -------------------------------------------------------- sequence state

@@ -57,6 +57,8 @@ struct ec_problem {
     double *xs_d = nullptr, *sj = nullptr, *sc = nullptr, *ac = nullptr, *bcpl = nullptr;
     double *rb[2] = {}, *wb[2] = {}, *sb[2] = {}, *pv = nullptr;
     double *w = nullptr, *t2 = nullptr, *t3 = nullptr, *t4 = nullptr;
+    // scratch of a second history push running in the same launches
+    double *w_b = nullptr, *t2_b = nullptr, *t3_b = nullptr, *t4_b = nullptr;
     // grad-div weight of the SPE projection: eta0 = half the mean diagonal of
     // K_n on edges off the conductor, scaled by the caller's factor
     double eta0 = 0.0, gauge_rel = 1.0;
@@ -79,7 +81,7 @@ struct ec_problem {
     SeqDev *seq_d = nullptr;
     Ctrl *ctrl_d = nullptr;
     CgCtl *cg_d = nullptr;
-    double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr;
+    double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr, *part_md_b = nullptr;
     unsigned *bar = nullptr;     // grid-barrier counters of the PCG tail kernel
     int tail_blocks = 0;         // persistent tail grid (0: no tail available)
     // 2.5D PCG iteration (large grids): column width, planes per block, tile
@@ -329,7 +331,7 @@ extern "C" int32_t ec_destroy(ec_handle h)
 
 // -------------------------------------------------------- workspace
 // Layout (256-byte aligned pieces):
-//   13 FP64 edge vectors, 5 FP32 edge vectors, per sequence 2 (cap+1) basis
+//   20 FP64 edge vectors, 8 FP32 edge vectors, per sequence 2 (cap+1) basis
 //   columns, tables (classes, cell materials, conducting slots, 1/M_sigma),
 //   sequence states, barrier, control block, reduction partials.
 static int64_t layout(ec_problem *h, int cap, char *base)
@@ -343,7 +345,7 @@ static int64_t layout(ec_problem *h, int cap, char *base)
     const int64_t ld = align_up(h->npad, 64);
     double **vecs[] = {&h->xs_d, &h->sj, &h->sc, &h->ac, &h->bcpl, &h->rb[0], &h->rb[1],
                        &h->wb[0], &h->wb[1], &h->sb[0], &h->sb[1], &h->pv, &h->w, &h->t2,
-                       &h->t3, &h->t4};
+                       &h->t3, &h->t4, &h->w_b, &h->t2_b, &h->t3_b, &h->t4_b};
     for (double **v : vecs) *v = (double *)take(ld * 8);
     float **fv[] = {&h->frb[0], &h->frb[1], &h->fwb[0], &h->fwb[1], &h->fsb[0], &h->fsb[1],
                     &h->fpv, &h->fd};
@@ -360,6 +362,7 @@ static int64_t layout(ec_problem *h, int cap, char *base)
     h->cg_d = (CgCtl *)take(2 * sizeof(CgCtl));
     h->part_cg = (double *)take(2 * 4 * (int64_t)kMaxBlocks * 8);
     h->part_md = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
+    h->part_md_b = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
     h->part_ref = (double *)take(2 * (int64_t)kMaxBlocks * 8);
     h->bar = (unsigned *)take((int64_t)kBarWords * kBarStride * sizeof(unsigned));
     h->ld = ld;
@@ -536,16 +539,16 @@ static void seq_eta_ensure(ec_problem *h, int seq, int method, double eta)
     h->seq_eta[seq] = eta;
 }
 
-static MdArgs md_args(ec_problem *h)
+static MdArgs md_args(ec_problem *h, double *part = nullptr)
 {
     MdArgs m{};
     m.ld = h->ld;
-    m.part = h->part_md;
+    m.part = part ? part : h->part_md;
     m.n = h->npad;
     return m;
 }
 
-static LcArgs lc_args(ec_problem *h, int seq)
+static LcArgs lc_args(ec_problem *h, int seq, double *part = nullptr)
 {
     LcArgs l{};
     SeqDev *sd = h->seq_d + seq;
@@ -557,14 +560,27 @@ static LcArgs lc_args(ec_problem *h, int seq)
     l.cB = sd->cB;
     l.a1 = &sd->a1;
     l.a2 = &sd->a2;
-    l.part = h->part_md;
+    l.part = part ? part : h->part_md;
     l.n = h->npad;
     return l;
 }
 
+static SmallArgs small_args(ec_problem *h, int seq, int op, const double *part,
+                            ec_solve_info *info = nullptr)
+{
+    SmallArgs a{};
+    a.seq = h->seq_d + seq;
+    a.op = op;
+    a.part = part;
+    a.nvals = kMdStride;
+    a.tol = h->dep_tol;
+    a.info = info;
+    return a;
+}
+
 static void dense(ec_problem *h, int seq, int op, ec_solve_info *info = nullptr)
 {
-    small(h->seq_d + seq, op, h->part_md, kMdStride, h->dep_tol, info, h->st);
+    small(small_args(h, seq, op, h->part_md, info), h->st);
 }
 
 // x0 and r0 = b - K_n x0 (into rb[0]) from the history of seq (eqs. 10, 14)
@@ -587,62 +603,98 @@ static void seq_start(ec_problem *h, int seq, int method, const double *b, const
     lincomb(l, st);
 }
 
-// append solution x to the history of seq
-static void seq_push(ec_problem *h, int seq, int method, const double *x)
+// Append solution xs[i] to the history of sequence seqs[i], for n = 1 or 2
+// independent sequences with the same method: every kernel of the push is
+// one launch for both (each sequence has its own scratch vectors and
+// partials and sees exactly the single-sequence grid).
+static void seq_push_n(ec_problem *h, int n, const int *seqs, int method,
+                       const double *const *xs)
 {
-    SeqDev *sd = h->seq_d + seq;
     hipStream_t st = h->st;
-    double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
+    double *wv[2] = {h->w, h->w_b}, *t2v[2] = {h->t2, h->t2_b}, *t3v[2] = {h->t3, h->t3_b};
+    double *t4v[2] = {h->t4, h->t4_b}, *pv[2] = {h->part_md, h->part_md_b};
+    const bool two = n == 2;
     if (method == EC_SV_POD) {
         // snapshot into the ring slot with its K_n product, then a Gram row
-        spmv_slot(h->g, x, h->t3, KQ, Q, &sd->slot_new, h->ld, nullptr, st);
-        MdArgs m = md_args(h);
-        m.A = Q;
-        m.kp = &sd->npush;
-        m.B[0] = {x, nullptr};
-        m.B[1] = {h->t3, nullptr};
-        m.nb = 2;
-        multidot(m, st);
-        dense(h, seq, OP_POD_PUSH);
+        SlotArgs sa[2];
+        MdArgs m[2];
+        SmallArgs sm[2];
+        for (int i = 0; i < n; ++i) {
+            SeqDev *sd = h->seq_d + seqs[i];
+            sa[i] = SlotArgs{xs[i], t3v[i], basis_KQ(h, seqs[i]), basis_Q(h, seqs[i]), nullptr,
+                             &sd->slot_new, nullptr, 0.0};
+            m[i] = md_args(h, pv[i]);
+            m[i].A = basis_Q(h, seqs[i]);
+            m[i].kp = &sd->npush;
+            m[i].B[0] = {xs[i], nullptr};
+            m[i].B[1] = {t3v[i], nullptr};
+            m[i].nb = 2;
+            sm[i] = small_args(h, seqs[i], OP_POD_PUSH, pv[i]);
+        }
+        spmv_slots(h->g, h->ld, sa[0], st, two ? &sa[1] : nullptr);
+        multidot(m[0], st, two ? &m[1] : nullptr);
+        small(sm[0], st, two ? &sm[1] : nullptr);
         return;
     }
     // SPE: two classical Gram-Schmidt passes against the orthogonal basis
-    MdArgs m = md_args(h);
-    m.A = Q;
-    m.kp = &sd->k;
-    m.a_extra = x;
-    m.B[0] = {x, nullptr};
-    m.nb = 1;
-    multidot(m, st);
-    dense(h, seq, OP_SPE_PUSH1);
-    LcArgs l = lc_args(h, seq);
-    l.v1 = x;
-    l.y1 = h->w;
-    l.active = &sd->active;
-    l.want_dots = 1;
-    lincomb(l, st);
-    dense(h, seq, OP_SPE_PUSH2);
-    l.v1 = h->w;
-    l.y1 = h->t2;
-    l.want_dots = 0;
-    lincomb(l, st);
-    dense(h, seq, OP_SPE_PUSH3);
-    // the new column and its K_n product into their slots, and in the same
-    // pass (K_n + eta D^T D) t2 for the new column of Q^T (K_n + eta D^T D) Q:
-    // the grad-div term keeps the projection from amplifying the gradient
-    // part of the window
-    const double eta = h->seq_eta[seq];
-    spmv_slot_penal(h->g, h->t2, h->t4, KQ, Q, &sd->slot_new, h->ld, eta, &sd->active, st);
-    const double *kq = h->t4;
-    MdArgs m2 = md_args(h);
-    m2.A = Q;
-    m2.kp = &sd->ncol_md;
-    m2.B[0] = {kq, nullptr};
-    m2.nb = 1;
-    m2.active = &sd->active;
-    multidot(m2, st);
-    dense(h, seq, OP_SPE_PUSH4);
-    rotate(Q, KQ, h->ld, h->npad, sd, st);
+    MdArgs m[2], m2[2];
+    LcArgs l1[2], l2[2];
+    SlotArgs sa[2];
+    RotArgs ro[2];
+    SmallArgs s1[2], s2[2], s3[2], s4[2];
+    for (int i = 0; i < n; ++i) {
+        const int seq = seqs[i];
+        SeqDev *sd = h->seq_d + seq;
+        double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
+        m[i] = md_args(h, pv[i]);
+        m[i].A = Q;
+        m[i].kp = &sd->k;
+        m[i].a_extra = xs[i];
+        m[i].B[0] = {xs[i], nullptr};
+        m[i].nb = 1;
+        s1[i] = small_args(h, seq, OP_SPE_PUSH1, pv[i]);
+        l1[i] = lc_args(h, seq, pv[i]);
+        l1[i].v1 = xs[i];
+        l1[i].y1 = wv[i];
+        l1[i].active = &sd->active;
+        l1[i].want_dots = 1;
+        s2[i] = small_args(h, seq, OP_SPE_PUSH2, pv[i]);
+        l2[i] = l1[i];
+        l2[i].v1 = wv[i];
+        l2[i].y1 = t2v[i];
+        l2[i].want_dots = 0;
+        s3[i] = small_args(h, seq, OP_SPE_PUSH3, pv[i]);
+        // the new column and its K_n product into their slots, and in the
+        // same pass (K_n + eta D^T D) t2 for the new column of
+        // Q^T (K_n + eta D^T D) Q: the grad-div term keeps the projection
+        // from amplifying the gradient part of the window
+        sa[i] = SlotArgs{t2v[i], nullptr, KQ, Q, t4v[i], &sd->slot_new, &sd->active,
+                         h->seq_eta[seq]};
+        m2[i] = md_args(h, pv[i]);
+        m2[i].A = Q;
+        m2[i].kp = &sd->ncol_md;
+        m2[i].B[0] = {t4v[i], nullptr};
+        m2[i].nb = 1;
+        m2[i].active = &sd->active;
+        s4[i] = small_args(h, seq, OP_SPE_PUSH4, pv[i]);
+        ro[i] = RotArgs{Q, KQ, sd};
+    }
+    multidot(m[0], st, two ? &m[1] : nullptr);
+    small(s1[0], st, two ? &s1[1] : nullptr);
+    lincomb(l1[0], st, two ? &l1[1] : nullptr);
+    small(s2[0], st, two ? &s2[1] : nullptr);
+    lincomb(l2[0], st, two ? &l2[1] : nullptr);
+    small(s3[0], st, two ? &s3[1] : nullptr);
+    spmv_slots(h->g, h->ld, sa[0], st, two ? &sa[1] : nullptr);
+    multidot(m2[0], st, two ? &m2[1] : nullptr);
+    small(s4[0], st, two ? &s4[1] : nullptr);
+    rotate(ro[0], h->ld, h->npad, st, two ? &ro[1] : nullptr);
+}
+
+// append solution x to the history of seq
+static void seq_push(ec_problem *h, int seq, int method, const double *x)
+{
+    seq_push_n(h, 1, &seq, method, &x);
 }
 
 // ------------------------------------------------------------- solve
@@ -1106,7 +1158,7 @@ static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const e
     step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st);
     const int meth = o->start_method;
     int32_t rc = do_solve(h, EC_SEQ_SRC, meth, o->window, o->pod_kmax, o->pod_eps, h->xs_d,
-                          &h->ctrl_d->scale, h->sj, &o->solve, info, true);
+                          &h->ctrl_d->scale, h->sj, &o->solve, info, false);
     if (rc) return rc;
     UpdArgs u{};
     u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
@@ -1115,8 +1167,15 @@ static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const e
     update_c(u, st);
     if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
     rc = do_solve(h, EC_SEQ_CPL, meth, o->window, o->pod_kmax, o->pod_eps, h->bcpl, nullptr, h->sc,
-                  &o->solve, info ? info + 1 : nullptr, true);
+                  &o->solve, info ? info + 1 : nullptr, false);
     if (rc) return rc;
+    // both histories grow in the same launches: the source history is next
+    // read by the source solve of the following step
+    if (meth == EC_SV_SPE || meth == EC_SV_POD) {
+        const int seqs[2] = {EC_SEQ_SRC, EC_SEQ_CPL};
+        const double *xs[2] = {h->sj, h->sc};
+        seq_push_n(h, 2, seqs, meth, xs);
+    }
     finish_state(h->g, A, h->ac, h->sj, h->sc, h->ctrl_d, 1, st);
     return launch_check(h, "step");
 }

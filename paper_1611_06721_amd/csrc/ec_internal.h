@@ -94,14 +94,19 @@ struct Vec2 {
 
 void spmv(const Geo &g, const double *x, double *y, const int lo[3], const int hi[3],
           hipStream_t st);
-// y = K_n x over the full grid; if slot != nullptr also copy y to
-// ycopy + (*slot)*ld and x to xcopy + (*slot)*ld; skipped when *active == 0
-void spmv_slot(const Geo &g, const double *x, double *y, double *ycopy, double *xcopy,
-               const int *slot, int64_t ld, const int *active, hipStream_t st);
-// ycopy/xcopy columns as spmv_slot, and ypen = K_n x + eta D^T D x on
-// nonconducting edges (= K_n x for eta = 0); skipped when *active == 0
-void spmv_slot_penal(const Geo &g, const double *x, double *ypen, double *ycopy, double *xcopy,
-                     const int *slot, int64_t ld, double eta, const int *active, hipStream_t st);
+// y (if given) = K_n x over the full grid; ycopy/xcopy (if given) receive
+// K_n x and x at column *slot (ld apart); ypen (if given) = K_n x + eta D^T D x
+// on nonconducting edges (D: divergence at free nodes; K_n x for eta = 0).
+// Nothing happens for a set whose *active == 0.  s1: a second, independent
+// set in the same launch.
+struct SlotArgs {
+    const double *x;
+    double *y, *ycopy, *xcopy, *ypen;
+    const int *slot, *active;
+    double eta;
+};
+void spmv_slots(const Geo &g, int64_t ld, const SlotArgs &s, hipStream_t st,
+                const SlotArgs *s1 = nullptr);
 void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st);
 
 // PCG start modes
@@ -185,7 +190,8 @@ struct MdArgs {
     double *part;
     int64_t n;
 };
-void multidot(const MdArgs &a, hipStream_t st);
+// a1: a second, independent argument set run in the same launch
+void multidot(const MdArgs &a, hipStream_t st, const MdArgs *a1 = nullptr);
 
 // y1 = a1 v1 + sum cA_i A_i ; y2 = a2 s2 v2 - ... (see kernel) with partial norms
 struct LcArgs {
@@ -203,10 +209,14 @@ struct LcArgs {
     double *part;
     int64_t n;
 };
-void lincomb(const LcArgs &a, hipStream_t st);
+void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1 = nullptr);
 
 // in-place basis rotation: columns j < k' of A (and B) become sum_i rot[i,j] A_i
-void rotate(double *A, double *B, int64_t ld, int64_t n, const SeqDev *seq, hipStream_t st);
+struct RotArgs {
+    double *A, *B;
+    const SeqDev *seq;
+};
+void rotate(const RotArgs &r, int64_t ld, int64_t n, hipStream_t st, const RotArgs *r1 = nullptr);
 
 // dense steps on one sequence: one block reduces the partial rows of the
 // preceding basis product and runs the step
@@ -221,8 +231,15 @@ enum {
     OP_POD_START,       // vals: X_i^T b (count)
     OP_RESET
 };
-void small(SeqDev *seq, int op, const double *part, int nvals, double tol, ec_solve_info *info,
-           hipStream_t st);
+struct SmallArgs {
+    SeqDev *seq;
+    int op;
+    const double *part;      // partial rows of the producing product (value-major)
+    int nvals;
+    double tol;              // dependency threshold (SPE push)
+    ec_solve_info *info;
+};
+void small(const SmallArgs &a, hipStream_t st, const SmallArgs *a1 = nullptr);
 void seq_reset(SeqDev *seq, hipStream_t st);
 
 // nonlinear a_c update (eq. 6) / K_c + K_cn apply over conducting edges

@@ -42,27 +42,41 @@ __device__ __forceinline__ double free_div(const Geo &g, const double *__restric
 }
 
 // ------------------------------------------------------------- SpMV kernel
+// One argument set: y (if given) = K_n x; ycopy/xcopy (if given) receive K_n x
+// and x at column *slot (ld apart); ypen (if given, FP64) = K_n x + eta D^T D x
+// on nonconducting edges (K_n x for eta = 0); nothing when *active == 0.
+template <typename T>
+struct SpmvArgs {
+    const T *x;
+    T *y, *ycopy, *xcopy, *ypen;
+    const int *slot, *active;
+    double eta;
+};
+
 // Blocks are mapped XCD-contiguously (block b runs on XCD b % 8): each XCD
 // sweeps one slab, so the k +- 1 planes of the stencil stay in its own L2.
-// y (if given) = K_n x; ycopy/xcopy (if given) receive K_n x and x at column
-// *slot; ypen (if given, FP64) = K_n x + eta D^T D x on nonconducting edges,
-// the same value the grad-div kernel forms from K_n x.
+// Block row blockIdx.y serves argument set a0 or a1 over the same box.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_spmv(Geo g, const T *__restrict__ x, T *__restrict__ y, int lo0, int lo1, int lo2,
-           int ex, int ey, int ez, int tiles, int tpx, T *__restrict__ ycopy,
-           T *__restrict__ xcopy, const int *slot, int64_t ld, const int *active,
-           T *__restrict__ ypen, double eta)
+    k_spmv(Geo g, int lo0, int lo1, int lo2, int ex, int ey, int ez, int tiles, int tpx,
+           int64_t ld, SpmvArgs<T> a0, SpmvArgs<T> a1)
 {
-    if (active && !*active) return;
+    const SpmvArgs<T> &a = blockIdx.y ? a1 : a0;
+    if (a.active && !*a.active) return;
     const int b = blockIdx.x, tile = (b & 7) * tpx + (b >> 3);
     if (tile >= tiles) return;
     const int64_t t = (int64_t)tile * kTile + threadIdx.x;
     const int64_t cnt = (int64_t)ex * ey * ez;
     if (t >= cnt) return;
-    if (slot) {
-        if (ycopy) ycopy += (int64_t)(*slot) * ld;
-        if (xcopy) xcopy += (int64_t)(*slot) * ld;
+    const T *__restrict__ x = a.x;
+    T *__restrict__ y = a.y;
+    T *__restrict__ ycopy = a.ycopy;
+    T *__restrict__ xcopy = a.xcopy;
+    T *__restrict__ ypen = a.ypen;
+    const double eta = a.eta;
+    if (a.slot) {
+        if (ycopy) ycopy += (int64_t)(*a.slot) * ld;
+        if (xcopy) xcopy += (int64_t)(*a.slot) * ld;
     }
     const int64_t exy = (int64_t)ex * ey;
     const int kk = (int)((double)t * (1.0 / (double)exy) + 1e-7);
@@ -72,7 +86,7 @@ __global__ void __launch_bounds__(256)
     const int i = ii + lo0, j = jj + lo1, k = kk + lo2;
     const int64_t n = ((int64_t)k * g.py + j) * g.px + i;
     T q[3];
-    curlcurl_node<T>(g, n, [&](int, int64_t a) { return x[a]; }, q[0], q[1], q[2]);
+    curlcurl_node<T>(g, n, [&](int, int64_t ia) { return x[ia]; }, q[0], q[1], q[2]);
     double d0 = 0.0, dh[3] = {0.0, 0.0, 0.0};
     if constexpr (std::is_same<T, double>::value) {
         if (ypen && eta > 0.0) {
@@ -101,44 +115,54 @@ __global__ void __launch_bounds__(256)
 }
 
 template <typename T>
-static void spmv_launch_box(const Geo &g, const T *x, T *y, const int lo[3], const int ext[3],
-                            hipStream_t st, T *ycopy, T *xcopy, const int *slot, int64_t ld,
-                            const int *active, T *ypen = nullptr, double eta = 0.0)
+static void spmv_launch_box(const Geo &g, const int lo[3], const int ext[3], int64_t ld,
+                            const SpmvArgs<T> &a0, const SpmvArgs<T> *a1, hipStream_t st)
 {
     const int64_t cnt = (int64_t)ext[0] * ext[1] * ext[2];
     if (cnt <= 0) return;
     const int tiles = (int)((cnt + kTile - 1) / kTile);
     const int tpx = (tiles + 7) / 8;
-    hipLaunchKernelGGL(k_spmv<T>, dim3(8 * tpx), dim3(kTile), 0, st, g, x, y, lo[0], lo[1],
-                       lo[2], ext[0], ext[1], ext[2], tiles, tpx, ycopy, xcopy, slot, ld, active,
-                       ypen, eta);
+    hipLaunchKernelGGL(k_spmv<T>, dim3(8 * tpx, a1 ? 2 : 1), dim3(kTile), 0, st, g, lo[0], lo[1],
+                       lo[2], ext[0], ext[1], ext[2], tiles, tpx, ld, a0, a1 ? *a1 : a0);
 }
 
 void spmv(const Geo &g, const double *x, double *y, const int lo[3], const int hi[3],
           hipStream_t st)
 {
     const int ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
-    spmv_launch_box<double>(g, x, y, lo, ext, st, nullptr, nullptr, nullptr, 0, nullptr);
+    SpmvArgs<double> a{};
+    a.x = x;
+    a.y = y;
+    spmv_launch_box<double>(g, lo, ext, 0, a, nullptr, st);
 }
 
-void spmv_slot(const Geo &g, const double *x, double *y, double *ycopy, double *xcopy,
-               const int *slot, int64_t ld, const int *active, hipStream_t st)
+static SpmvArgs<double> slot_args(const SlotArgs &s)
 {
-    const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
-    spmv_launch_box<double>(g, x, y, lo, ext, st, ycopy, xcopy, slot, ld, active);
+    SpmvArgs<double> a{};
+    a.x = s.x; a.y = s.y; a.ycopy = s.ycopy; a.xcopy = s.xcopy; a.ypen = s.ypen;
+    a.slot = s.slot; a.active = s.active; a.eta = s.eta;
+    return a;
 }
 
-void spmv_slot_penal(const Geo &g, const double *x, double *ypen, double *ycopy, double *xcopy,
-                     const int *slot, int64_t ld, double eta, const int *active, hipStream_t st)
+void spmv_slots(const Geo &g, int64_t ld, const SlotArgs &s, hipStream_t st, const SlotArgs *s1)
 {
     const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
-    spmv_launch_box<double>(g, x, nullptr, lo, ext, st, ycopy, xcopy, slot, ld, active, ypen, eta);
+    const SpmvArgs<double> a0 = slot_args(s);
+    if (s1) {
+        const SpmvArgs<double> a1 = slot_args(*s1);
+        spmv_launch_box<double>(g, lo, ext, ld, a0, &a1, st);
+    } else {
+        spmv_launch_box<double>(g, lo, ext, ld, a0, nullptr, st);
+    }
 }
 
 void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st)
 {
     const int lo[3] = {0, 0, 0}, ext[3] = {g.nx + 1, g.ny + 1, g.nz + 1};
-    spmv_launch_box<float>(g, x, y, lo, ext, st, nullptr, nullptr, nullptr, 0, nullptr);
+    SpmvArgs<float> a{};
+    a.x = x;
+    a.y = y;
+    spmv_launch_box<float>(g, lo, ext, 0, a, nullptr, st);
 }
 
 // ------------------------------------------------------------------- CG
