@@ -488,11 +488,12 @@ __device__ __forceinline__ void load4(const double *col, int64_t row, int64_t n,
     }
 }
 
-// Block row blockIdx.y serves argument set a0 or a1 (independent sequences
-// in one launch); each set sees exactly the single-set grid.
-__global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a0, MdArgs a1)
+// The kernels below come in two launches: argument sets a0 / a1 by value
+// (block row blockIdx.y picks one) or row blockIdx.y of a device table
+// (independent sequences or instances in one launch); each set sees exactly
+// the single-set grid.
+__device__ __forceinline__ void multidot_body(const MdArgs &a)
 {
-    const MdArgs a = blockIdx.y ? a1 : a0;
     if (a.active && !*a.active) return;
     __shared__ double red[kMdWaves][32][4];
     const int k = a.kp ? *a.kp : a.kfix;
@@ -570,19 +571,34 @@ __global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a0, MdArgs a1)
     }
 }
 
+__global__ void __launch_bounds__(kMdThreads) k_multidot(MdArgs a0, MdArgs a1)
+{
+    const MdArgs a = blockIdx.y ? a1 : a0;
+    multidot_body(a);
+}
+
+__global__ void __launch_bounds__(kMdThreads) k_multidot_tab(const MdArgs *tab)
+{
+    multidot_body(tab[blockIdx.y]);
+}
+
 void multidot(const MdArgs &a, hipStream_t st, const MdArgs *a1)
 {
     hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st, a,
                        a1 ? *a1 : a);
 }
 
+void multidot_tab(const MdArgs *tab, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_multidot_tab, dim3(kMdBlocks, n), dim3(kMdThreads), 0, st, tab);
+}
+
 // ----------------------------------------------------- linear combinations
 // y1 = a1 v1 + sum_{i<k} cA_i A_i        (y1 may be column *slot of A)
 // y2 = a2 s2 v2 + sum_{i<k} cB_i B_i
 // partials: [0..k) A_i^T y1 (want_dots), then |y1|^2, |y2|^2, |s2 v2|^2
-__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs set0, LcArgs set1)
+__device__ __forceinline__ void lincomb_body(const LcArgs &a)
 {
-    const LcArgs &a = blockIdx.y ? set1 : set0;
     if (a.active && !*a.active) return;
     __shared__ double sA[kMaxWin], sB[kMaxWin];
     __shared__ double lds[kMaxWin + 3][kMdWaves];
@@ -655,19 +671,33 @@ __global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs set0, LcArgs set1
     }
 }
 
+__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs set0, LcArgs set1)
+{
+    lincomb_body(blockIdx.y ? set1 : set0);
+}
+
+__global__ void __launch_bounds__(kMdThreads) k_lincomb_tab(const LcArgs *tab)
+{
+    lincomb_body(tab[blockIdx.y]);
+}
+
 void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1)
 {
     hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st, a,
                        a1 ? *a1 : a);
 }
 
+void lincomb_tab(const LcArgs *tab, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lincomb_tab, dim3(kMdBlocks, n), dim3(kMdThreads), 0, st, tab);
+}
+
 // In-place rotation of the first rot_in columns of A (and B) into rot_k
 // columns: A'_j = sum_i rot[i][j] A_i.
-__global__ void __launch_bounds__(kMdThreads)
-    k_rotate(RotArgs r0, RotArgs r1, int64_t ld, int64_t n)
+__device__ __forceinline__ void rotate_body(const RotArgs &r)
 {
-    const RotArgs &r = blockIdx.y ? r1 : r0;
     double *A = r.A, *B = r.B;
+    const int64_t ld = r.ld, n = r.n;
     const SeqDev *seq = r.seq;
     if (!seq->rotate) return;
     __shared__ double R[K * K];
@@ -693,17 +723,31 @@ __global__ void __launch_bounds__(kMdThreads)
     }
 }
 
-void rotate(const RotArgs &r, int64_t ld, int64_t n, hipStream_t st, const RotArgs *r1)
+__global__ void __launch_bounds__(kMdThreads) k_rotate(RotArgs r0, RotArgs r1)
+{
+    rotate_body(blockIdx.y ? r1 : r0);
+}
+
+__global__ void __launch_bounds__(kMdThreads) k_rotate_tab(const RotArgs *tab)
+{
+    rotate_body(tab[blockIdx.y]);
+}
+
+void rotate(const RotArgs &r, hipStream_t st, const RotArgs *r1)
 {
     hipLaunchKernelGGL(k_rotate, dim3(kMdBlocks, r1 ? 2 : 1), dim3(kMdThreads), 0, st, r,
-                       r1 ? *r1 : r, ld, n);
+                       r1 ? *r1 : r);
+}
+
+void rotate_tab(const RotArgs *tab, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rotate_tab, dim3(kMdBlocks, n), dim3(kMdThreads), 0, st, tab);
 }
 
 // One block per argument set (blockIdx.y): reduce the partial rows of the
 // preceding basis product, then run the dense step `op` of the sequence.
-__global__ void __launch_bounds__(256) k_small(SmallArgs s0, SmallArgs s1)
+__device__ __forceinline__ void small_body(const SmallArgs &sa)
 {
-    const SmallArgs &sa = blockIdx.y ? s1 : s0;
     SeqDev *sq = sa.seq;
     const int op = sa.op, nvals = sa.nvals;
     const double *part = sa.part;
@@ -726,9 +770,24 @@ __global__ void __launch_bounds__(256) k_small(SmallArgs s0, SmallArgs s1)
     small_op(sq, op, val, sa.tol, sa.info);
 }
 
+__global__ void __launch_bounds__(256) k_small(SmallArgs s0, SmallArgs s1)
+{
+    small_body(blockIdx.y ? s1 : s0);
+}
+
+__global__ void __launch_bounds__(256) k_small_tab(const SmallArgs *tab)
+{
+    small_body(tab[blockIdx.y]);
+}
+
 void small(const SmallArgs &a, hipStream_t st, const SmallArgs *a1)
 {
     hipLaunchKernelGGL(k_small, dim3(1, a1 ? 2 : 1), dim3(256), 0, st, a, a1 ? *a1 : a);
+}
+
+void small_tab(const SmallArgs *tab, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_small_tab, dim3(1, n), dim3(256), 0, st, tab);
 }
 
 // -------------------------------------------------------- sequence state

@@ -583,112 +583,131 @@ static void dense(ec_problem *h, int seq, int op, ec_solve_info *info = nullptr)
     small(small_args(h, seq, op, h->part_md, info), h->st);
 }
 
-// x0 and r0 = b - K_n x0 (into rb[0]) from the history of seq (eqs. 10, 14)
+// Arguments of the three launches of a start vector: x0 and r0 = b - K_n x0
+// (into rb[0]) from the history of seq (eqs. 10, 14)
+struct StartArgs {
+    MdArgs m;
+    SmallArgs s;
+    LcArgs l;
+};
+
+static StartArgs seq_start_args(ec_problem *h, int seq, int method, const double *b,
+                                const double *bscale, double *x0, ec_solve_info *info)
+{
+    SeqDev *sd = h->seq_d + seq;
+    StartArgs a;
+    a.m = md_args(h);
+    a.m.A = basis_Q(h, seq);
+    a.m.kp = method == EC_SV_POD ? &sd->count : &sd->k;
+    a.m.B[0] = {b, bscale};
+    a.m.nb = 1;
+    a.s = small_args(h, seq, method == EC_SV_POD ? OP_POD_START : OP_SPE_START, h->part_md, info);
+    a.l = lc_args(h, seq);
+    a.l.v2 = {b, bscale};
+    a.l.y1 = x0;
+    a.l.y2 = h->rb[0];
+    return a;
+}
+
 static void seq_start(ec_problem *h, int seq, int method, const double *b, const double *bscale,
                       double *x0, ec_solve_info *info)
 {
-    SeqDev *sd = h->seq_d + seq;
-    hipStream_t st = h->st;
-    MdArgs m = md_args(h);
-    m.A = basis_Q(h, seq);
-    m.kp = method == EC_SV_POD ? &sd->count : &sd->k;
-    m.B[0] = {b, bscale};
-    m.nb = 1;
-    multidot(m, st);
-    dense(h, seq, method == EC_SV_POD ? OP_POD_START : OP_SPE_START, info);
-    LcArgs l = lc_args(h, seq);
-    l.v2 = {b, bscale};
-    l.y1 = x0;
-    l.y2 = h->rb[0];
-    lincomb(l, st);
+    const StartArgs a = seq_start_args(h, seq, method, b, bscale, x0, info);
+    multidot(a.m, h->st);
+    small(a.s, h->st);
+    lincomb(a.l, h->st);
 }
 
-// Append solution xs[i] to the history of sequence seqs[i], for n = 1 or 2
-// independent sequences with the same method: every kernel of the push is
-// one launch for both (each sequence has its own scratch vectors and
-// partials and sees exactly the single-sequence grid).
+// Arguments of the launches of a history push of solution x into seq, with
+// scratch set `set` (0 or 1: two pushes may share launches).  SPE: two
+// classical Gram-Schmidt passes against the orthogonal basis, the new column
+// and its K_n product into their slots with (K_n + eta D^T D) t2 for the new
+// column of Q^T (K_n + eta D^T D) Q (the grad-div term keeps the projection
+// from amplifying the gradient part of the window), then the window downdate.
+// POD: the snapshot and its K_n product into the ring slot, a Gram row.
+struct PushArgs {
+    MdArgs m, m2;
+    LcArgs l1, l2;
+    SlotArgs sa;
+    RotArgs ro;
+    SmallArgs s1, s2, s3, s4;
+};
+
+static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *x, int set)
+{
+    double *w = set ? h->w_b : h->w, *t2 = set ? h->t2_b : h->t2;
+    double *t3 = set ? h->t3_b : h->t3, *t4 = set ? h->t4_b : h->t4;
+    double *part = set ? h->part_md_b : h->part_md;
+    SeqDev *sd = h->seq_d + seq;
+    double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
+    PushArgs a{};
+    if (method == EC_SV_POD) {
+        a.sa = SlotArgs{x, t3, KQ, Q, nullptr, &sd->slot_new, nullptr, 0.0};
+        a.m = md_args(h, part);
+        a.m.A = Q;
+        a.m.kp = &sd->npush;
+        a.m.B[0] = {x, nullptr};
+        a.m.B[1] = {t3, nullptr};
+        a.m.nb = 2;
+        a.s1 = small_args(h, seq, OP_POD_PUSH, part);
+        return a;
+    }
+    a.m = md_args(h, part);
+    a.m.A = Q;
+    a.m.kp = &sd->k;
+    a.m.a_extra = x;
+    a.m.B[0] = {x, nullptr};
+    a.m.nb = 1;
+    a.s1 = small_args(h, seq, OP_SPE_PUSH1, part);
+    a.l1 = lc_args(h, seq, part);
+    a.l1.v1 = x;
+    a.l1.y1 = w;
+    a.l1.active = &sd->active;
+    a.l1.want_dots = 1;
+    a.s2 = small_args(h, seq, OP_SPE_PUSH2, part);
+    a.l2 = a.l1;
+    a.l2.v1 = w;
+    a.l2.y1 = t2;
+    a.l2.want_dots = 0;
+    a.s3 = small_args(h, seq, OP_SPE_PUSH3, part);
+    a.sa = SlotArgs{t2, nullptr, KQ, Q, t4, &sd->slot_new, &sd->active, h->seq_eta[seq]};
+    a.m2 = md_args(h, part);
+    a.m2.A = Q;
+    a.m2.kp = &sd->ncol_md;
+    a.m2.B[0] = {t4, nullptr};
+    a.m2.nb = 1;
+    a.m2.active = &sd->active;
+    a.s4 = small_args(h, seq, OP_SPE_PUSH4, part);
+    a.ro = RotArgs{Q, KQ, sd, h->ld, h->npad};
+    return a;
+}
+
+// Append solution xs[i] to the history of sequence seqs[i] (n = 1 or 2
+// independent sequences of one problem, same method): every kernel of the
+// push is one launch for both, each with its own scratch and partials.
 static void seq_push_n(ec_problem *h, int n, const int *seqs, int method,
                        const double *const *xs)
 {
     hipStream_t st = h->st;
-    double *wv[2] = {h->w, h->w_b}, *t2v[2] = {h->t2, h->t2_b}, *t3v[2] = {h->t3, h->t3_b};
-    double *t4v[2] = {h->t4, h->t4_b}, *pv[2] = {h->part_md, h->part_md_b};
-    const bool two = n == 2;
+    PushArgs a[2];
+    for (int i = 0; i < n; ++i) a[i] = seq_push_args(h, seqs[i], method, xs[i], i);
+    const PushArgs *b = n == 2 ? &a[1] : nullptr;
     if (method == EC_SV_POD) {
-        // snapshot into the ring slot with its K_n product, then a Gram row
-        SlotArgs sa[2];
-        MdArgs m[2];
-        SmallArgs sm[2];
-        for (int i = 0; i < n; ++i) {
-            SeqDev *sd = h->seq_d + seqs[i];
-            sa[i] = SlotArgs{xs[i], t3v[i], basis_KQ(h, seqs[i]), basis_Q(h, seqs[i]), nullptr,
-                             &sd->slot_new, nullptr, 0.0};
-            m[i] = md_args(h, pv[i]);
-            m[i].A = basis_Q(h, seqs[i]);
-            m[i].kp = &sd->npush;
-            m[i].B[0] = {xs[i], nullptr};
-            m[i].B[1] = {t3v[i], nullptr};
-            m[i].nb = 2;
-            sm[i] = small_args(h, seqs[i], OP_POD_PUSH, pv[i]);
-        }
-        spmv_slots(h->g, h->ld, sa[0], st, two ? &sa[1] : nullptr);
-        multidot(m[0], st, two ? &m[1] : nullptr);
-        small(sm[0], st, two ? &sm[1] : nullptr);
+        spmv_slots(h->g, h->ld, a[0].sa, st, b ? &b->sa : nullptr);
+        multidot(a[0].m, st, b ? &b->m : nullptr);
+        small(a[0].s1, st, b ? &b->s1 : nullptr);
         return;
     }
-    // SPE: two classical Gram-Schmidt passes against the orthogonal basis
-    MdArgs m[2], m2[2];
-    LcArgs l1[2], l2[2];
-    SlotArgs sa[2];
-    RotArgs ro[2];
-    SmallArgs s1[2], s2[2], s3[2], s4[2];
-    for (int i = 0; i < n; ++i) {
-        const int seq = seqs[i];
-        SeqDev *sd = h->seq_d + seq;
-        double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
-        m[i] = md_args(h, pv[i]);
-        m[i].A = Q;
-        m[i].kp = &sd->k;
-        m[i].a_extra = xs[i];
-        m[i].B[0] = {xs[i], nullptr};
-        m[i].nb = 1;
-        s1[i] = small_args(h, seq, OP_SPE_PUSH1, pv[i]);
-        l1[i] = lc_args(h, seq, pv[i]);
-        l1[i].v1 = xs[i];
-        l1[i].y1 = wv[i];
-        l1[i].active = &sd->active;
-        l1[i].want_dots = 1;
-        s2[i] = small_args(h, seq, OP_SPE_PUSH2, pv[i]);
-        l2[i] = l1[i];
-        l2[i].v1 = wv[i];
-        l2[i].y1 = t2v[i];
-        l2[i].want_dots = 0;
-        s3[i] = small_args(h, seq, OP_SPE_PUSH3, pv[i]);
-        // the new column and its K_n product into their slots, and in the
-        // same pass (K_n + eta D^T D) t2 for the new column of
-        // Q^T (K_n + eta D^T D) Q: the grad-div term keeps the projection
-        // from amplifying the gradient part of the window
-        sa[i] = SlotArgs{t2v[i], nullptr, KQ, Q, t4v[i], &sd->slot_new, &sd->active,
-                         h->seq_eta[seq]};
-        m2[i] = md_args(h, pv[i]);
-        m2[i].A = Q;
-        m2[i].kp = &sd->ncol_md;
-        m2[i].B[0] = {t4v[i], nullptr};
-        m2[i].nb = 1;
-        m2[i].active = &sd->active;
-        s4[i] = small_args(h, seq, OP_SPE_PUSH4, pv[i]);
-        ro[i] = RotArgs{Q, KQ, sd};
-    }
-    multidot(m[0], st, two ? &m[1] : nullptr);
-    small(s1[0], st, two ? &s1[1] : nullptr);
-    lincomb(l1[0], st, two ? &l1[1] : nullptr);
-    small(s2[0], st, two ? &s2[1] : nullptr);
-    lincomb(l2[0], st, two ? &l2[1] : nullptr);
-    small(s3[0], st, two ? &s3[1] : nullptr);
-    spmv_slots(h->g, h->ld, sa[0], st, two ? &sa[1] : nullptr);
-    multidot(m2[0], st, two ? &m2[1] : nullptr);
-    small(s4[0], st, two ? &s4[1] : nullptr);
-    rotate(ro[0], h->ld, h->npad, st, two ? &ro[1] : nullptr);
+    multidot(a[0].m, st, b ? &b->m : nullptr);
+    small(a[0].s1, st, b ? &b->s1 : nullptr);
+    lincomb(a[0].l1, st, b ? &b->l1 : nullptr);
+    small(a[0].s2, st, b ? &b->s2 : nullptr);
+    lincomb(a[0].l2, st, b ? &b->l2 : nullptr);
+    small(a[0].s3, st, b ? &b->s3 : nullptr);
+    spmv_slots(h->g, h->ld, a[0].sa, st, b ? &b->sa : nullptr);
+    multidot(a[0].m2, st, b ? &b->m2 : nullptr);
+    small(a[0].s4, st, b ? &b->s4 : nullptr);
+    rotate(a[0].ro, st, b ? &b->ro : nullptr);
 }
 
 // append solution x to the history of seq
@@ -882,7 +901,8 @@ static int32_t run_refined(ec_problem *h, int seq, const double *b, const double
 // start vector of a solve (eqs. 10, 14 for SPE / POD) and the PCG start mode
 static int32_t solve_prepare(ec_problem *h, int seq, int method, int window, int kmax,
                              double eps, const double *b, const double *bscale, double *x,
-                             const ec_solve_opts *o, ec_solve_info *info, int *mode)
+                             const ec_solve_opts *o, ec_solve_info *info, int *mode,
+                             bool launch_start = true)
 {
     if (o->precision != EC_PREC_FP64 && o->precision != EC_PREC_FP32_REFINED)
         return fail(h, EC_ERR_ARG, "unknown precision %d", o->precision);
@@ -896,7 +916,7 @@ static int32_t solve_prepare(ec_problem *h, int seq, int method, int window, int
             return fail(h, EC_ERR_ARG, "window must be 1..%d (the bound window_cap)", h->cap);
         seq_ensure(h, seq, method, window, kmax, eps);
         seq_eta_ensure(h, seq, method, spe_eta(h, o->precision));
-        seq_start(h, seq, method, b, bscale, x, info);
+        if (launch_start) seq_start(h, seq, method, b, bscale, x, info);
         *mode = START_DEV;
     } else {
         return fail(h, EC_ERR_ARG, "unknown start method %d", method);
@@ -1660,11 +1680,23 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
 // the histories run as each problem's own kernels; the PCG iterations of all
 // solves run in one launch per iteration (k_cg_iter_batch), each instance on
 // its own slice of the grid with exactly the single-instance arithmetic.
+// Start vectors and history pushes of all instances run as one launch per
+// kernel from device tables of per-instance arguments (one block row each).
+struct BasisTab {
+    MdArgs *m_start, *m, *m2;
+    SmallArgs *s_start, *s1, *s2, *s3, *s4;
+    LcArgs *l_start, *l1, *l2;
+    SlotTab *sa;
+    RotArgs *ro;
+};
+
 struct ec_batch_s {
     std::vector<ec_problem *> inst;
     hipStream_t st = nullptr;
     CgArgs<double> *tab_d[2] = {};                 // per sequence: SRC, CPL
     std::vector<CgArgs<double>> tab[2];
+    BasisTab btab[2];                              // per sequence, device tables
+    int slot_tpx = 1;                              // slot SpMV grid of the largest instance
     int *inst_d = nullptr, *off_d = nullptr, *flag_d = nullptr;
     int total_blocks = 0, max_blocks = 0;
     int tiles_per_block = 1;
@@ -1686,7 +1718,25 @@ static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_
     int *im = (int *)take(maxb * 4);
     int *of = (int *)take(n * 4);
     int *fl = (int *)take(64);
+    BasisTab bt[2];
+    for (BasisTab &t : bt) {
+        t.m_start = (MdArgs *)take(n * sizeof(MdArgs));
+        t.m = (MdArgs *)take(n * sizeof(MdArgs));
+        t.m2 = (MdArgs *)take(n * sizeof(MdArgs));
+        t.s_start = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.s1 = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.s2 = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.s3 = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.s4 = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.l_start = (LcArgs *)take(n * sizeof(LcArgs));
+        t.l1 = (LcArgs *)take(n * sizeof(LcArgs));
+        t.l2 = (LcArgs *)take(n * sizeof(LcArgs));
+        t.sa = (SlotTab *)take(n * sizeof(SlotTab));
+        t.ro = (RotArgs *)take(n * sizeof(RotArgs));
+    }
     if (b) {
+        b->btab[0] = bt[0];
+        b->btab[1] = bt[1];
         b->tab_d[0] = t0;
         b->tab_d[1] = t1;
         b->inst_d = im;
@@ -1718,22 +1768,78 @@ static int32_t batch_apply_tiles(ec_batch_s *b, int f)
     return EC_OK;
 }
 
-// per-instance PCG arguments of the source / coupling solves (device tables)
-static int32_t batch_tables(ec_batch_s *b, const ec_solve_opts *o)
+// per-instance PCG, start-vector and history-push arguments of the source /
+// coupling solves (device tables); the sequences are configured first, so
+// the tables carry the current grad-div weights
+static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so)
 {
+    const ec_solve_opts *o = &so->solve;
+    const int meth = so->start_method;
+    const bool basis = meth == EC_SV_SPE || meth == EC_SV_POD;
+    ec_problem *h0 = b->inst[0];
+    b->slot_tpx = 1;
     for (int s = 0; s < 2; ++s) {
+        const int seq = s == 0 ? EC_SEQ_SRC : EC_SEQ_CPL;
         b->tab[s].clear();
+        std::vector<MdArgs> ms, m1, m2;
+        std::vector<SmallArgs> ss, s1, s2, s3, s4;
+        std::vector<LcArgs> ls, l1, l2;
+        std::vector<SlotTab> sa;
+        std::vector<RotArgs> ro;
         for (ec_problem *h : b->inst) {
             if (s == 0) b->tab[s].push_back(cg64_args(h, EC_SEQ_SRC, h->xs_d, &h->ctrl_d->scale,
                                                       h->sj, o, nullptr));
             else b->tab[s].push_back(cg64_args(h, EC_SEQ_CPL, h->bcpl, nullptr, h->sc, o, nullptr));
+            if (!basis) continue;
+            seq_ensure(h, seq, meth, so->window, so->pod_kmax, so->pod_eps);
+            seq_eta_ensure(h, seq, meth, spe_eta(h, o->precision));
+            const CgArgs<double> &a = b->tab[s].back();
+            const StartArgs st = seq_start_args(h, seq, meth, a.b, a.bscale, a.x, nullptr);
+            ms.push_back(st.m);
+            ss.push_back(st.s);
+            ls.push_back(st.l);
+            const PushArgs pa = seq_push_args(h, seq, meth, a.x, 0);
+            m1.push_back(pa.m);
+            m2.push_back(pa.m2);
+            s1.push_back(pa.s1);
+            s2.push_back(pa.s2);
+            s3.push_back(pa.s3);
+            s4.push_back(pa.s4);
+            l1.push_back(pa.l1);
+            l2.push_back(pa.l2);
+            sa.push_back(SlotTab{h->g, h->ld, pa.sa});
+            ro.push_back(pa.ro);
+            b->slot_tpx = std::max(b->slot_tpx, spmv_slot_tpx(h->g));
         }
-        ec_problem *h0 = b->inst[0];
         HIP_TRY(h0, hipMemcpyAsync(b->tab_d[s], b->tab[s].data(),
                                    b->tab[s].size() * sizeof(CgArgs<double>),
                                    hipMemcpyHostToDevice, b->st));
+        if (!basis) continue;
+        const BasisTab &t = b->btab[s];
+        auto up = [&](void *dst, const void *src, size_t bytes) -> int32_t {
+            HIP_TRY(h0, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->st));
+            return EC_OK;
+        };
+        int32_t rc = EC_OK;
+        const size_t n = b->inst.size();
+        if (!rc) rc = up(t.m_start, ms.data(), n * sizeof(MdArgs));
+        if (!rc) rc = up(t.m, m1.data(), n * sizeof(MdArgs));
+        if (!rc) rc = up(t.m2, m2.data(), n * sizeof(MdArgs));
+        if (!rc) rc = up(t.s_start, ss.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.s1, s1.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.s2, s2.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.s3, s3.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.s4, s4.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.l_start, ls.data(), n * sizeof(LcArgs));
+        if (!rc) rc = up(t.l1, l1.data(), n * sizeof(LcArgs));
+        if (!rc) rc = up(t.l2, l2.data(), n * sizeof(LcArgs));
+        if (!rc) rc = up(t.sa, sa.data(), n * sizeof(SlotTab));
+        if (!rc) rc = up(t.ro, ro.data(), n * sizeof(RotArgs));
+        if (rc) return rc;
+        // the host vectors go out of scope: finish the copies first
+        HIP_TRY(h0, hipStreamSynchronize(b->st));
     }
-    HIP_TRY(b->inst[0], hipStreamSynchronize(b->st));
+    HIP_TRY(h0, hipStreamSynchronize(b->st));
     return EC_OK;
 }
 
@@ -1742,15 +1848,22 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
     const int seq = s == 0 ? EC_SEQ_SRC : EC_SEQ_CPL;
     const int meth = o->start_method;
     const int n = (int)b->inst.size();
+    const bool basis = meth == EC_SV_SPE || meth == EC_SV_POD;
+    const BasisTab &t = b->btab[s];
+    std::vector<int> modes(n);
     for (int i = 0; i < n; ++i) {
         ec_problem *h = b->inst[i];
         const CgArgs<double> &a = b->tab[s][i];
-        int mode = 0;
         int32_t rc = solve_prepare(h, seq, meth, o->window, o->pod_kmax, o->pod_eps, a.b, a.bscale,
-                                   a.x, &o->solve, nullptr, &mode);
+                                   a.x, &o->solve, nullptr, &modes[i], false);
         if (rc) return rc;
-        cg64_init(h, a, mode);
     }
+    if (basis) {                 // start vectors of all instances (eqs. 10, 14)
+        multidot_tab(t.m_start, n, b->st);
+        small_tab(t.s_start, n, b->st);
+        lincomb_tab(t.l_start, n, b->st);
+    }
+    for (int i = 0; i < n; ++i) cg64_init(b->inst[i], b->tab[s][i], modes[i]);
     const int maxit = o->solve.maxit;
     int issued = 0;
     ec_problem *h0 = b->inst[0];
@@ -1774,10 +1887,22 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
             chunk = std::min(2 * chunk, 256);
         }
     }
-    for (int i = 0; i < n; ++i) {
-        ec_problem *h = b->inst[i];
-        cg_fin<double>(b->tab[s][i], issued, b->st);
-        if (meth == EC_SV_SPE || meth == EC_SV_POD) seq_push(h, seq, meth, b->tab[s][i].x);
+    for (int i = 0; i < n; ++i) cg_fin<double>(b->tab[s][i], issued, b->st);
+    if (meth == EC_SV_POD) {     // histories of all instances
+        spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
+        multidot_tab(t.m, n, b->st);
+        small_tab(t.s1, n, b->st);
+    } else if (meth == EC_SV_SPE) {
+        multidot_tab(t.m, n, b->st);
+        small_tab(t.s1, n, b->st);
+        lincomb_tab(t.l1, n, b->st);
+        small_tab(t.s2, n, b->st);
+        lincomb_tab(t.l2, n, b->st);
+        small_tab(t.s3, n, b->st);
+        spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
+        multidot_tab(t.m2, n, b->st);
+        small_tab(t.s4, n, b->st);
+        rotate_tab(t.ro, n, b->st);
     }
     return launch_check(h0, "batch solve");
 }
@@ -1882,7 +2007,7 @@ extern "C" int32_t ec_batch_step(ec_batch b, int64_t m, const double *dt, double
 {
     int32_t rc = batch_check(b, dt, A, opts);
     if (rc) return rc;
-    rc = batch_tables(b, &opts->solve);
+    rc = batch_tables(b, opts);
     if (rc) return rc;
     return batch_step_impl(b, m, dt, A, opts);
 }
@@ -1893,7 +2018,7 @@ extern "C" int32_t ec_batch_run(ec_batch b, int64_t m0, int64_t nsteps, const do
     int32_t rc = batch_check(b, dt, A, opts);
     if (rc) return rc;
     if (nsteps < 0) return fail(nullptr, EC_ERR_ARG, "nsteps must be >= 0");
-    rc = batch_tables(b, &opts->solve);
+    rc = batch_tables(b, opts);
     if (rc) return rc;
     for (int64_t s = 0; s < nsteps; ++s) {
         rc = batch_step_impl(b, m0 < 0 ? -1 : m0 + 1 + s, dt, A, opts);
@@ -1913,7 +2038,7 @@ extern "C" int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *
             seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
             seq_eta_ensure(h, s, opts->start_method, spe_eta(h, opts->solve.precision));
         }
-    rc = batch_tables(b, &opts->solve);
+    rc = batch_tables(b, opts);
     if (rc) return rc;
     ec_problem *h0 = b->inst[0];
     hipGraph_t graph = nullptr;

@@ -107,6 +107,16 @@ struct SlotArgs {
 };
 void spmv_slots(const Geo &g, int64_t ld, const SlotArgs &s, hipStream_t st,
                 const SlotArgs *s1 = nullptr);
+// one set per instance of a batch, each on its own grid (full box)
+struct SlotTab {
+    Geo g;
+    int64_t ld;
+    SlotArgs s;
+};
+// grid covers the largest instance; tpx_max = max over the table of
+// ceil(tiles / 8) with tiles = ceil((nx+1)(ny+1)(nz+1) / 256)
+void spmv_slots_tab(const SlotTab *tab, int n, int tpx_max, hipStream_t st);
+int spmv_slot_tpx(const Geo &g);
 void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st);
 
 // PCG start modes
@@ -190,8 +200,10 @@ struct MdArgs {
     double *part;
     int64_t n;
 };
-// a1: a second, independent argument set run in the same launch
+// a1: a second, independent argument set run in the same launch; the _tab
+// launchers run the n sets of a device table (block row y = set y)
 void multidot(const MdArgs &a, hipStream_t st, const MdArgs *a1 = nullptr);
+void multidot_tab(const MdArgs *tab, int n, hipStream_t st);
 
 // y1 = a1 v1 + sum cA_i A_i ; y2 = a2 s2 v2 - ... (see kernel) with partial norms
 struct LcArgs {
@@ -210,13 +222,16 @@ struct LcArgs {
     int64_t n;
 };
 void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1 = nullptr);
+void lincomb_tab(const LcArgs *tab, int n, hipStream_t st);
 
 // in-place basis rotation: columns j < k' of A (and B) become sum_i rot[i,j] A_i
 struct RotArgs {
     double *A, *B;
     const SeqDev *seq;
+    int64_t ld, n;
 };
-void rotate(const RotArgs &r, int64_t ld, int64_t n, hipStream_t st, const RotArgs *r1 = nullptr);
+void rotate(const RotArgs &r, hipStream_t st, const RotArgs *r1 = nullptr);
+void rotate_tab(const RotArgs *tab, int n, hipStream_t st);
 
 // dense steps on one sequence: one block reduces the partial rows of the
 // preceding basis product and runs the step
@@ -240,6 +255,7 @@ struct SmallArgs {
     ec_solve_info *info;
 };
 void small(const SmallArgs &a, hipStream_t st, const SmallArgs *a1 = nullptr);
+void small_tab(const SmallArgs *tab, int n, hipStream_t st);
 void seq_reset(SeqDev *seq, hipStream_t st);
 
 // nonlinear a_c update (eq. 6) / K_c + K_cn apply over conducting edges

@@ -55,13 +55,11 @@ struct SpmvArgs {
 
 // Blocks are mapped XCD-contiguously (block b runs on XCD b % 8): each XCD
 // sweeps one slab, so the k +- 1 planes of the stencil stay in its own L2.
-// Block row blockIdx.y serves argument set a0 or a1 over the same box.
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_spmv(Geo g, int lo0, int lo1, int lo2, int ex, int ey, int ez, int tiles, int tpx,
-           int64_t ld, SpmvArgs<T> a0, SpmvArgs<T> a1)
+__device__ __forceinline__ void spmv_box(const Geo &g, int lo0, int lo1, int lo2, int ex, int ey,
+                                         int ez, int tiles, int tpx, int64_t ld,
+                                         const SpmvArgs<T> &a)
 {
-    const SpmvArgs<T> &a = blockIdx.y ? a1 : a0;
     if (a.active && !*a.active) return;
     const int b = blockIdx.x, tile = (b & 7) * tpx + (b >> 3);
     if (tile >= tiles) return;
@@ -112,6 +110,44 @@ __global__ void __launch_bounds__(256)
             }
         }
     }
+}
+
+// Block row blockIdx.y serves argument set a0 or a1 over the same box.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_spmv(Geo g, int lo0, int lo1, int lo2, int ex, int ey, int ez, int tiles, int tpx,
+           int64_t ld, SpmvArgs<T> a0, SpmvArgs<T> a1)
+{
+    const SpmvArgs<T> &a = blockIdx.y ? a1 : a0;
+    spmv_box<T>(g, lo0, lo1, lo2, ex, ey, ez, tiles, tpx, ld, a);
+}
+
+// Block row blockIdx.y serves instance y of a batch over its full box, with
+// the block-to-tile map of its own launch (blocks past its grid leave).
+__global__ void __launch_bounds__(256) k_spmv_slot_tab(const SlotTab *tab)
+{
+    const SlotTab &e = tab[blockIdx.y];
+    const Geo g = e.g;
+    const int ex = g.nx + 1, ey = g.ny + 1, ez = g.nz + 1;
+    const int64_t cnt = (int64_t)ex * ey * ez;
+    const int tiles = (int)((cnt + kTile - 1) / kTile), tpx = (tiles + 7) / 8;
+    if ((int)(blockIdx.x >> 3) >= tpx) return;
+    SpmvArgs<double> a{};
+    a.x = e.s.x; a.y = e.s.y; a.ycopy = e.s.ycopy; a.xcopy = e.s.xcopy; a.ypen = e.s.ypen;
+    a.slot = e.s.slot; a.active = e.s.active; a.eta = e.s.eta;
+    spmv_box<double>(g, 0, 0, 0, ex, ey, ez, tiles, tpx, e.ld, a);
+}
+
+int spmv_slot_tpx(const Geo &g)
+{
+    const int64_t cnt = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    const int tiles = (int)((cnt + kTile - 1) / kTile);
+    return (tiles + 7) / 8;
+}
+
+void spmv_slots_tab(const SlotTab *tab, int n, int tpx_max, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_spmv_slot_tab, dim3(8 * tpx_max, n), dim3(kTile), 0, st, tab);
 }
 
 template <typename T>
