@@ -1863,7 +1863,13 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
         small_tab(t.s_start, n, b->st);
         lincomb_tab(t.l_start, n, b->st);
     }
-    for (int i = 0; i < n; ++i) cg64_init(b->inst[i], b->tab[s][i], modes[i]);
+    // PCG inits of all instances (same start method, so the same mode)
+    if (modes[0] == START_X) {
+        cg_init_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, START_X, b->st);
+        cg_init_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, START_R2, b->st);
+    } else {
+        cg_init_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, modes[0], b->st);
+    }
     const int maxit = o->solve.maxit;
     int issued = 0;
     ec_problem *h0 = b->inst[0];
@@ -1887,7 +1893,7 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
             chunk = std::min(2 * chunk, 256);
         }
     }
-    for (int i = 0; i < n; ++i) cg_fin<double>(b->tab[s][i], issued, b->st);
+    cg_fin_batch(b->tab_d[s], n, issued, b->st);
     if (meth == EC_SV_POD) {     // histories of all instances
         spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
         multidot_tab(t.m, n, b->st);

@@ -178,6 +178,10 @@ void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st);
 void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
                    int it, hipStream_t st);
 // *flag (device int) = 1 if every solve of tab[0..n) finished before iteration it
+// init (in `mode`) / final record of every solve of a batch in one launch
+void cg_init_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
+                   int mode, hipStream_t st);
+void cg_fin_batch(const CgArgs<double> *tab, int n, int iters, hipStream_t st);
 void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t st);
 // blocks of the persistent tail (at most two per CU, all resident at once, a
 // multiple of 8; 0 on failure)

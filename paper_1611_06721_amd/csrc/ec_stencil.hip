@@ -217,21 +217,20 @@ __device__ __forceinline__ void sum_part(const double *P, int nb, double (&t)[4]
 // Init, phase START_X: r0 = s b - K_n x0, partials (|r0|^2, |b|^2) into part[1].
 // Init, phases ZERO / R / R2 / DEV: w0 = K_n D^-1 r0 and partials
 // (gamma0 = r0^T D^-1 r0, delta0 = w0^T D^-1 r0, |r0|^2, |b|^2) into part[0].
+// Block bid of nb of the init in mode `mode`.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
+__device__ __forceinline__ void cg_init_body(const CgArgs<T> &a, int mode, int bid, int nb)
 {
-    if (a.skip && *a.skip) return;
     const Geo &g = a.g;
     const int64_t S = g.S;
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
     const double bs = a.bscale ? *a.bscale : 1.0;
-    int mode = a.mode;
     if (mode == START_DEV) mode = a.seq->zero_start ? START_ZERO : START_R;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     T *r0 = a.rb[0];
     double *P0 = a.part, *P1 = a.part + 4 * (int64_t)kMaxBlocks;
     if (mode == START_X) {
-        for_tiles(a.tiles, S, [&](int64_t n) {
+        for_tiles_b(a.tiles, S, bid, nb, [&](int64_t n) {
             int i, j, k;
             decode(g, n, i, j, k);
             T q[3];
@@ -248,16 +247,16 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
         });
         block_sum<4>(v);
         if (threadIdx.x == 0)
-            for (int q = 0; q < 4; ++q) P1[(int64_t)blockIdx.x * 4 + q] = v[q];
+            for (int q = 0; q < 4; ++q) P1[(int64_t)bid * 4 + q] = v[q];
         return;
     }
     bool zero_all = false;
     if (mode == START_R2) {
         double t[4];
-        sum_part(P1, gridDim.x, t);
+        sum_part(P1, nb, t);
         zero_all = t[1] == 0.0;   // b = 0: the pseudo-inverse solution is x = 0
     }
-    for_tiles(a.tiles, S, [&](int64_t n) {
+    for_tiles_b(a.tiles, S, bid, nb, [&](int64_t n) {
         int i, j, k;
         decode(g, n, i, j, k);
         T w[3] = {(T)0, (T)0, (T)0};
@@ -300,8 +299,8 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
     });
     block_sum<4>(v);
     if (threadIdx.x == 0) {
-        for (int q = 0; q < 4; ++q) P0[(int64_t)blockIdx.x * 4 + q] = v[q];
-        if (blockIdx.x == 0) {
+        for (int q = 0; q < 4; ++q) P0[(int64_t)bid * 4 + q] = v[q];
+        if (bid == 0) {
             CgCtl c0{};
             c0.done = 0;
             c0.status = EC_OK;
@@ -310,8 +309,26 @@ __global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
         }
     }
     // arrival and release words of the tail kernel's barrier
-    if (blockIdx.x == 0 && a.bar)
+    if (bid == 0 && a.bar)
         for (int q = threadIdx.x; q < kBarWords; q += blockDim.x) a.bar[(int64_t)q * kBarStride] = 0u;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_init(CgArgs<T> a)
+{
+    if (a.skip && *a.skip) return;
+    cg_init_body<T>(a, a.mode, blockIdx.x, gridDim.x);
+}
+
+// The init of every solve of a batch in one launch (block map as in
+// k_cg_iter_batch), all in mode `mode`.
+__global__ void __launch_bounds__(256)
+    k_cg_init_batch(const CgArgs<double> *__restrict__ tab, const int *__restrict__ inst,
+                    const int *__restrict__ off, int mode)
+{
+    const int i = inst[blockIdx.x];
+    const CgArgs<double> &a = tab[i];
+    cg_init_body<double>(a, mode, blockIdx.x - off[i], a.blocks);
 }
 
 // State entering kernel i from the reduced partials t = (gamma, delta, rho,
@@ -540,6 +557,13 @@ void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, i
                    int it, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cg_iter_batch, dim3(total_blocks), dim3(kTile), 0, st, tab, inst, off, it);
+}
+
+void cg_init_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
+                   int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_init_batch, dim3(total_blocks), dim3(kTile), 0, st, tab, inst, off,
+                       mode);
 }
 
 void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t st)
@@ -810,9 +834,8 @@ __global__ void __launch_bounds__(256) k_cg_tail(CgArgs<T> a, int it0, unsigned 
 // After `iters` iteration kernels: final decision on the last iterate, the
 // solve record and the per-sequence counters (one block).
 template <typename T>
-__global__ void __launch_bounds__(256) k_cg_fin(CgArgs<T> a, int iters)
+__device__ __forceinline__ void cg_fin_body(const CgArgs<T> &a, int iters)
 {
-    if (a.skip && *a.skip) return;
     double t[4];
     sum_part(a.part + (int64_t)(iters & 1) * 4 * kMaxBlocks, a.blocks, t);
     if (threadIdx.x != 0) return;
@@ -851,6 +874,24 @@ __global__ void __launch_bounds__(256) k_cg_fin(CgArgs<T> a, int iters)
         // outer FP64 residual check decides the status
         if (!a.accum && st < a.ctrl->worst) a.ctrl->worst = st;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_fin(CgArgs<T> a, int iters)
+{
+    if (a.skip && *a.skip) return;
+    cg_fin_body<T>(a, iters);
+}
+
+// k_cg_fin of every solve of a batch: block row blockIdx.y serves tab[y]
+__global__ void __launch_bounds__(256) k_cg_fin_tab(const CgArgs<double> *tab, int iters)
+{
+    cg_fin_body<double>(tab[blockIdx.y], iters);
+}
+
+void cg_fin_batch(const CgArgs<double> *tab, int n, int iters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_fin_tab, dim3(1, n), dim3(256), 0, st, tab, iters);
 }
 
 template <typename T>
