@@ -1697,6 +1697,14 @@ struct ec_batch_s {
     std::vector<CgArgs<double>> tab[2];
     BasisTab btab[2];                              // per sequence, device tables
     int slot_tpx = 1;                              // slot SpMV grid of the largest instance
+    // per-instance step control, conducting update, coupling right-hand
+    // side and state assembly (device tables) and their largest grids
+    StepArgs *step_tab = nullptr;
+    UpdArgs *upd_tab = nullptr;
+    BoxTab *box_tab = nullptr;
+    FinArgs *fin_tab = nullptr;
+    int nc_max = 0, box_tpx = 0;
+    int64_t npad_max = 0;
     int *inst_d = nullptr, *off_d = nullptr, *flag_d = nullptr;
     int total_blocks = 0, max_blocks = 0;
     int tiles_per_block = 1;
@@ -1734,7 +1742,15 @@ static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_
         t.sa = (SlotTab *)take(n * sizeof(SlotTab));
         t.ro = (RotArgs *)take(n * sizeof(RotArgs));
     }
+    StepArgs *stp = (StepArgs *)take(n * sizeof(StepArgs));
+    UpdArgs *upd = (UpdArgs *)take(n * sizeof(UpdArgs));
+    BoxTab *box = (BoxTab *)take(n * sizeof(BoxTab));
+    FinArgs *fin = (FinArgs *)take(n * sizeof(FinArgs));
     if (b) {
+        b->step_tab = stp;
+        b->upd_tab = upd;
+        b->box_tab = box;
+        b->fin_tab = fin;
         b->btab[0] = bt[0];
         b->btab[1] = bt[1];
         b->tab_d[0] = t0;
@@ -1771,12 +1787,54 @@ static int32_t batch_apply_tiles(ec_batch_s *b, int f)
 // per-instance PCG, start-vector and history-push arguments of the source /
 // coupling solves (device tables); the sequences are configured first, so
 // the tables carry the current grad-div weights
-static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so)
+static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double *dt,
+                            double *const *A)
 {
     const ec_solve_opts *o = &so->solve;
     const int meth = so->start_method;
     const bool basis = meth == EC_SV_SPE || meth == EC_SV_POD;
     ec_problem *h0 = b->inst[0];
+    const size_t ni = b->inst.size();
+    {
+        std::vector<StepArgs> stp(ni);
+        std::vector<UpdArgs> upd(ni);
+        std::vector<BoxTab> box(ni);
+        std::vector<FinArgs> fin(ni);
+        b->nc_max = 0;
+        b->box_tpx = 0;
+        b->npad_max = 0;
+        for (size_t i = 0; i < ni; ++i) {
+            ec_problem *h = b->inst[i];
+            stp[i] = StepArgs{h->ctrl_d, h->wf, h->amp, h->freq, h->tau, h->ramp, dt[i]};
+            UpdArgs &u = upd[i];
+            u = UpdArgs{};
+            u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d;
+            u.minv = h->minv_d; u.nc = h->nc; u.A = A[i]; u.sj = h->sj; u.sc = h->sc;
+            u.out = h->ac; u.dt = dt[i]; u.apply = 0; u.ctrl = h->ctrl_d;
+            BoxTab &bx = box[i];
+            bx = BoxTab{};
+            bx.g = h->g;
+            for (int c = 0; c < 3; ++c) {
+                bx.lo[c] = h->band_lo[c];
+                bx.ext[c] = h->has_cond ? h->band_hi[c] - h->band_lo[c] + 1 : 0;
+            }
+            bx.x = h->ac;
+            bx.y = h->bcpl;
+            fin[i] = FinArgs{h->g.npad, A[i], h->ac, h->sj, h->sc, h->ctrl_d};
+            b->nc_max = std::max(b->nc_max, h->nc);
+            b->box_tpx = std::max(b->box_tpx, spmv_box_tpx(bx.ext));
+            b->npad_max = std::max<int64_t>(b->npad_max, h->g.npad);
+        }
+        HIP_TRY(h0, hipMemcpyAsync(b->step_tab, stp.data(), ni * sizeof(StepArgs),
+                                   hipMemcpyHostToDevice, b->st));
+        HIP_TRY(h0, hipMemcpyAsync(b->upd_tab, upd.data(), ni * sizeof(UpdArgs),
+                                   hipMemcpyHostToDevice, b->st));
+        HIP_TRY(h0, hipMemcpyAsync(b->box_tab, box.data(), ni * sizeof(BoxTab),
+                                   hipMemcpyHostToDevice, b->st));
+        HIP_TRY(h0, hipMemcpyAsync(b->fin_tab, fin.data(), ni * sizeof(FinArgs),
+                                   hipMemcpyHostToDevice, b->st));
+        HIP_TRY(h0, hipStreamSynchronize(b->st));   // the host vectors go out of scope
+    }
     b->slot_tpx = 1;
     for (int s = 0; s < 2; ++s) {
         const int seq = s == 0 ? EC_SEQ_SRC : EC_SEQ_CPL;
@@ -1916,28 +1974,19 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
 static int32_t batch_step_impl(ec_batch_s *b, int64_t m, const double *dt, double *const *A,
                                const ec_step_opts *o)
 {
+    // the per-instance kernels of the step run from the device tables that
+    // batch_tables filled for these dt and A (one launch each for the batch)
+    (void)dt;
+    (void)A;
     const int n = (int)b->inst.size();
-    for (int i = 0; i < n; ++i) {
-        ec_problem *h = b->inst[i];
-        step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt[i], b->st);
-    }
+    step_begin_tab(b->step_tab, n, m, b->st);
     int32_t rc = batch_solve(b, 0, o);
     if (rc) return rc;
-    for (int i = 0; i < n; ++i) {
-        ec_problem *h = b->inst[i];
-        UpdArgs u{};
-        u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d;
-        u.minv = h->minv_d; u.nc = h->nc; u.A = A[i]; u.sj = h->sj; u.sc = h->sc; u.out = h->ac;
-        u.dt = dt[i]; u.apply = 0; u.ctrl = h->ctrl_d;
-        update_c(u, b->st);
-        if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, b->st);
-    }
+    update_c_tab(b->upd_tab, n, b->nc_max, b->st);
+    spmv_box_tab(b->box_tab, n, b->box_tpx, b->st);
     rc = batch_solve(b, 1, o);
     if (rc) return rc;
-    for (int i = 0; i < n; ++i) {
-        ec_problem *h = b->inst[i];
-        finish_state(h->g, A[i], h->ac, h->sj, h->sc, h->ctrl_d, 1, b->st);
-    }
+    finish_state_tab(b->fin_tab, n, b->npad_max, b->st);
     return launch_check(b->inst[0], "batch step");
 }
 
@@ -2013,7 +2062,7 @@ extern "C" int32_t ec_batch_step(ec_batch b, int64_t m, const double *dt, double
 {
     int32_t rc = batch_check(b, dt, A, opts);
     if (rc) return rc;
-    rc = batch_tables(b, opts);
+    rc = batch_tables(b, opts, dt, A);
     if (rc) return rc;
     return batch_step_impl(b, m, dt, A, opts);
 }
@@ -2024,7 +2073,7 @@ extern "C" int32_t ec_batch_run(ec_batch b, int64_t m0, int64_t nsteps, const do
     int32_t rc = batch_check(b, dt, A, opts);
     if (rc) return rc;
     if (nsteps < 0) return fail(nullptr, EC_ERR_ARG, "nsteps must be >= 0");
-    rc = batch_tables(b, opts);
+    rc = batch_tables(b, opts, dt, A);
     if (rc) return rc;
     for (int64_t s = 0; s < nsteps; ++s) {
         rc = batch_step_impl(b, m0 < 0 ? -1 : m0 + 1 + s, dt, A, opts);
@@ -2044,7 +2093,7 @@ extern "C" int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *
             seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
             seq_eta_ensure(h, s, opts->start_method, spe_eta(h, opts->solve.precision));
         }
-    rc = batch_tables(b, opts);
+    rc = batch_tables(b, opts, dt, A);
     if (rc) return rc;
     ec_problem *h0 = b->inst[0];
     hipGraph_t graph = nullptr;

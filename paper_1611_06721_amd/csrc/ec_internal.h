@@ -117,6 +117,16 @@ struct SlotTab {
 // ceil(tiles / 8) with tiles = ceil((nx+1)(ny+1)(nz+1) / 256)
 void spmv_slots_tab(const SlotTab *tab, int n, int tpx_max, hipStream_t st);
 int spmv_slot_tpx(const Geo &g);
+// y = K_n x over the box [lo, lo + ext) of each instance of a batch (ext of 0
+// cells: no work); grid from the largest box
+struct BoxTab {
+    Geo g;
+    int lo[3], ext[3];
+    const double *x;
+    double *y;
+};
+int spmv_box_tpx(const int ext[3]);
+void spmv_box_tab(const BoxTab *tab, int n, int tpx_max, hipStream_t st);
 void spmv_f(const Geo &g, const float *x, float *y, hipStream_t st);
 
 // PCG start modes
@@ -280,11 +290,29 @@ struct UpdArgs {
     const Ctrl *ctrl;
 };
 void update_c(const UpdArgs &a, hipStream_t st);
+// one launch for the n instances of a batch (nc_max: largest n_c)
+void update_c_tab(const UpdArgs *tab, int n, int nc_max, hipStream_t st);
 
 void finish_state(const Geo &g, double *A, const double *ac, const double *sj,
                   const double *sc, Ctrl *ctrl, int bump, hipStream_t st);
 void step_begin(Ctrl *ctrl, int64_t m, int wf, double amp, double freq, double tau,
                 int64_t ramp, double dt, hipStream_t st);
+// the same for the n instances of a batch, one launch each
+struct FinArgs {
+    int64_t n;
+    double *A;
+    const double *ac, *sj, *sc;
+    Ctrl *ctrl;
+};
+void finish_state_tab(const FinArgs *tab, int n, int64_t npad_max, hipStream_t st);
+struct StepArgs {
+    Ctrl *ctrl;
+    int wf;
+    double amp, freq, tau;
+    int64_t ramp;
+    double dt;
+};
+void step_begin_tab(const StepArgs *tab, int n, int64_t m, hipStream_t st);
 void fill(double *y, double v, int64_t n, hipStream_t st);
 void copy_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
 void mask_copy(const Geo &g, const double *x, double *y, int cls_keep, hipStream_t st);

@@ -138,6 +138,35 @@ __global__ void __launch_bounds__(256) k_spmv_slot_tab(const SlotTab *tab)
     spmv_box<double>(g, 0, 0, 0, ex, ey, ez, tiles, tpx, e.ld, a);
 }
 
+// y = K_n x over each instance's own box (block row per instance)
+__global__ void __launch_bounds__(256) k_spmv_box_tab(const BoxTab *tab)
+{
+    const BoxTab &e = tab[blockIdx.y];
+    const int64_t cnt = (int64_t)e.ext[0] * e.ext[1] * e.ext[2];
+    if (cnt <= 0) return;
+    const int tiles = (int)((cnt + kTile - 1) / kTile), tpx = (tiles + 7) / 8;
+    if ((int)(blockIdx.x >> 3) >= tpx) return;
+    SpmvArgs<double> a{};
+    a.x = e.x;
+    a.y = e.y;
+    spmv_box<double>(e.g, e.lo[0], e.lo[1], e.lo[2], e.ext[0], e.ext[1], e.ext[2], tiles, tpx, 0,
+                     a);
+}
+
+int spmv_box_tpx(const int ext[3])
+{
+    const int64_t cnt = (int64_t)ext[0] * ext[1] * ext[2];
+    if (cnt <= 0) return 0;
+    const int tiles = (int)((cnt + kTile - 1) / kTile);
+    return (tiles + 7) / 8;
+}
+
+void spmv_box_tab(const BoxTab *tab, int n, int tpx_max, hipStream_t st)
+{
+    if (tpx_max <= 0) return;
+    hipLaunchKernelGGL(k_spmv_box_tab, dim3(8 * tpx_max, n), dim3(kTile), 0, st, tab);
+}
+
 int spmv_slot_tpx(const Geo &g)
 {
     const int64_t cnt = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);

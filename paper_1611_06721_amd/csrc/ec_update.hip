@@ -45,7 +45,7 @@ __device__ __forceinline__ double face_flux(F V, int n, const int (&p)[3])
            V(n2, p[0], p[1], p[2]);
 }
 
-__global__ void __launch_bounds__(256) k_update(UpdArgs a)
+__device__ __forceinline__ void update_body(const UpdArgs &a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int e_idx = t >> 2, q = t & 3;
@@ -112,11 +112,30 @@ __global__ void __launch_bounds__(256) k_update(UpdArgs a)
     }
 }
 
+__global__ void __launch_bounds__(256) k_update(UpdArgs a)
+{
+    update_body(a);
+}
+
+// one instance of a batch per block row (the grid covers the largest n_c)
+__global__ void __launch_bounds__(256) k_update_tab(const UpdArgs *tab)
+{
+    update_body(tab[blockIdx.y]);
+}
+
 void update_c(const UpdArgs &a, hipStream_t st)
 {
     if (a.nc <= 0) return;
     const int64_t threads = 4 * (int64_t)a.nc;
     hipLaunchKernelGGL(k_update, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, a);
+}
+
+void update_c_tab(const UpdArgs *tab, int n, int nc_max, hipStream_t st)
+{
+    if (nc_max <= 0) return;
+    const int64_t threads = 4 * (int64_t)nc_max;
+    hipLaunchKernelGGL(k_update_tab, dim3((unsigned)((threads + 255) / 256), n), dim3(256), 0, st,
+                       tab);
 }
 
 // -------------------------------------------------- state and step control
@@ -138,9 +157,25 @@ void finish_state(const Geo &g, double *A, const double *ac, const double *sj, c
     hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(256), 0, st, g.npad, A, ac, sj, sc, ctrl, bump);
 }
 
+// one instance of a batch per block row (grid-stride over its own length)
+__global__ void k_finish_tab(const FinArgs *tab)
+{
+    const FinArgs &f = tab[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < f.n; e += stride)
+        f.A[e] = f.ac[e] + (f.sj[e] - f.sc[e]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) f.ctrl->n_steps += 1;
+}
+
+void finish_state_tab(const FinArgs *tab, int n, int64_t npad_max, hipStream_t st)
+{
+    const int blocks = (int)std::min<int64_t>((npad_max + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_finish_tab, dim3(blocks, n), dim3(256), 0, st, tab);
+}
+
 // i_S(t_m) of the source waveforms (DC, sine, linear ramp, 1 - exp(-t/tau)).
-__global__ void k_step_begin(Ctrl *ctrl, int64_t m_arg, int wf, double amp, double freq,
-                             double tau, int64_t ramp, double dt)
+__device__ __forceinline__ void step_begin_body(Ctrl *ctrl, int64_t m_arg, int wf, double amp,
+                                                double freq, double tau, int64_t ramp, double dt)
 {
     const int64_t m = m_arg >= 0 ? m_arg : ctrl->step + 1;
     ctrl->step = m;
@@ -155,6 +190,24 @@ __global__ void k_step_begin(Ctrl *ctrl, int64_t m_arg, int wf, double amp, doub
     default: s = 0.0;
     }
     ctrl->scale = s;
+}
+
+__global__ void k_step_begin(Ctrl *ctrl, int64_t m_arg, int wf, double amp, double freq,
+                             double tau, int64_t ramp, double dt)
+{
+    step_begin_body(ctrl, m_arg, wf, amp, freq, tau, ramp, dt);
+}
+
+// one instance of a batch per block row
+__global__ void k_step_begin_tab(const StepArgs *tab, int64_t m_arg)
+{
+    const StepArgs &s = tab[blockIdx.y];
+    step_begin_body(s.ctrl, m_arg, s.wf, s.amp, s.freq, s.tau, s.ramp, s.dt);
+}
+
+void step_begin_tab(const StepArgs *tab, int n, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_begin_tab, dim3(1, n), dim3(1), 0, st, tab, m);
 }
 
 void step_begin(Ctrl *ctrl, int64_t m, int wf, double amp, double freq, double tau, int64_t ramp,
