@@ -529,6 +529,121 @@ __device__ __forceinline__ void cg_update(const CgArgs<T> &a, int it, const CgCt
         for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
 }
 
+// The iteration with the node's stencil inputs loaded before the decision,
+// for launches where every block sweeps at most one tile: r, w, s at the 24
+// stencil positions and the node's own p, x are in flight while the block
+// reduces the previous partials, then t = D^-1 (r - alpha (w + beta s)), the
+// curl-curl and the update use exactly the expressions of cg_update.
+template <typename T>
+__device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int nprev,
+                                                CgCtl &s_c, double &s_beta, int bid)
+{
+    const Geo &g = a.g;
+    const int64_t S = g.S;
+    const bool first = it == 0;
+    const T *rc = a.rb[it & 1], *wc = a.wb[it & 1], *sp = a.sb[(it + 1) & 1];
+    T *rn = a.rb[(it + 1) & 1], *wn = a.wb[(it + 1) & 1], *sc = a.sb[it & 1];
+    double t[4];
+    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, nprev, t);
+    // this block's tile (the map of for_tiles_b with one tile per block)
+    const int tpx = (a.tiles + 7) >> 3, xcd = bid & 7, loc = bid >> 3;
+    const int tile = xcd * tpx + loc;
+    const int64_t n = (int64_t)tile * kTile + threadIdx.x;
+    const bool valid = loc < tpx && tile < a.tiles && n < S;
+    // stencil positions in the order of curlcurl_node: 8 of x, 8 of y, 8 of z
+    const int64_t oi = 1, oj = g.px, ok = (int64_t)g.px * g.py, last = 3 * S - 1;
+    const int64_t off[24] = {0, ok, -ok, ok - oi, -oi, oj, -oj, oj - oi,
+                             0, ok, -ok, -oj, ok - oj, oi, oi - oj, -oi,
+                             0, oj, oj - ok, -ok, -oj, oi, oi - ok, -oi};
+    T vr[24], vw[24], vs[24], op[3], ox[3];
+#pragma unroll
+    for (int q = 0; q < 24; ++q) {
+        vr[q] = vw[q] = vs[q] = (T)0;
+        if (valid) {
+            int64_t ix = (int64_t)(q >> 3) * S + n + off[q];
+            ix = ix < 0 ? 0 : (ix > last ? last : ix);
+            vr[q] = rc[ix];
+            vw[q] = wc[ix];
+            if (!first) vs[q] = sp[ix];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        op[c] = ox[c] = (T)0;
+        if (valid) {
+            if (!first) op[c] = a.p[c * S + n];
+            ox[c] = a.x[c * S + n];
+        }
+    }
+    if (cg_decide<T>(a, it, t, s_c, s_beta, bid)) return true;
+    const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
+    const T ta = (T)s_c.alpha, tb = (T)s_beta;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        int i, j, k;
+        decode(g, n, i, j, k);
+        T tv[24];
+#pragma unroll
+        for (int q = 0; q < 24; ++q) {
+            const T d = (T)dsel(dd, q >> 3);
+            tv[q] = first ? d * (vr[q] - ta * vw[q]) : d * (vr[q] - ta * (vw[q] + tb * vs[q]));
+        }
+        const T x0 = tv[0], x_kp = tv[1], x_km = tv[2], x_im_kp = tv[3], x_im = tv[4],
+                x_jp = tv[5], x_jm = tv[6], x_im_jp = tv[7];
+        const T y0 = tv[8], y_kp = tv[9], y_km = tv[10], y_jm = tv[11], y_jm_kp = tv[12],
+                y_ip = tv[13], y_ip_jm = tv[14], y_im = tv[15];
+        const T z0 = tv[16], z_jp = tv[17], z_jp_km = tv[18], z_km = tv[19], z_jm = tv[20],
+                z_ip = tv[21], z_ip_km = tv[22], z_im = tv[23];
+        const T Fx = y0 + z_jp - y_kp - z0;
+        const T Fx_km = y_km + z_jp_km - y0 - z_km;
+        const T Fx_jm = y_jm + z0 - y_jm_kp - z_jm;
+        const T Fy = z0 + x_kp - z_ip - x0;
+        const T Fy_km = z_km + x0 - z_ip_km - x_km;
+        const T Fy_im = z_im + x_im_kp - z0 - x_im;
+        const T Fz = x0 + y_ip - x_jp - y0;
+        const T Fz_jm = x_jm + y_ip_jm - x0 - y_jm;
+        const T Fz_im = x_im + y0 - x_im_jp - y_im;
+        const T wx = (T)g.wx, wy = (T)g.wy, wz = (T)g.wz;
+        const T w[3] = {wz * (Fz - Fz_jm) - wy * (Fy - Fy_km),
+                        wx * (Fx - Fx_km) - wz * (Fz - Fz_im),
+                        wy * (Fy - Fy_im) - wx * (Fx - Fx_jm)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t ix = c * S + n;
+            const T d = (T)dsel(dd, c);
+            const T rv = vr[8 * c], wv = vw[8 * c];
+            const T si = first ? wv : wv + tb * vs[8 * c];
+            const T pi = first ? d * rv : d * rv + tb * op[c];
+            a.x[ix] = ox[c] + ta * pi;
+            a.p[ix] = pi;
+            sc[ix] = si;
+            const T r1 = rv - ta * si;
+            rn[ix] = r1;
+            const T w1 = edge_cls(g, c, i, j, k, n) == 2 ? w[c] : (T)0;
+            wn[ix] = w1;
+            const double u1 = (double)d * (double)r1;
+            v[0] += u1 * (double)r1;
+            v[1] += (double)w1 * u1;
+            v[2] += (double)r1 * (double)r1;
+        }
+    }
+    block_sum<4>(v);
+    if (threadIdx.x == 0) {
+        double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
+        for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
+    }
+    return false;
+}
+
+// One tile per block on a grid of nb blocks: the hoisted form applies (the
+// same choice in the single, batched and tail kernels, so an iteration's
+// arithmetic is the same compiled code whichever kernel runs it).
+template <typename T>
+__device__ __forceinline__ bool one_tile_per_block(const CgArgs<T> &a, int nb)
+{
+    return (nb >> 3) >= ((a.tiles + 7) >> 3);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
 {
@@ -539,10 +654,14 @@ __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
         return;
     }
-    double t[4];
-    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, gridDim.x, t);
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
+    if (one_tile_per_block(a, gridDim.x)) {
+        cg_iter_hoisted<T>(a, it, gridDim.x, s_c, s_beta, blockIdx.x);
+        return;
+    }
+    double t[4];
+    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, gridDim.x, t);
     if (cg_decide<T>(a, it, t, s_c, s_beta, blockIdx.x)) return;
     cg_update<T>(a, it, s_c, s_beta, blockIdx.x, gridDim.x);
 }
@@ -562,10 +681,14 @@ __global__ void __launch_bounds__(256)
         if (bid == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
         return;
     }
-    double t[4];
-    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, a.blocks, t);
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
+    if (one_tile_per_block(a, a.blocks)) {
+        cg_iter_hoisted<double>(a, it, a.blocks, s_c, s_beta, bid);
+        return;
+    }
+    double t[4];
+    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, a.blocks, t);
     if (cg_decide<double>(a, it, t, s_c, s_beta, bid)) return;
     cg_update<double>(a, it, s_c, s_beta, bid, a.blocks);
 }
@@ -827,8 +950,10 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen)
 // iterations it0, it0+1, ... in one persistent launch, a grid barrier
 // between iterations, until the (uniform) convergence / maxit decision.
 // Ends by storing the final record in both control slots.
-template <typename T>
-__global__ void __launch_bounds__(256) k_cg_tail(CgArgs<T> a, int it0, unsigned *bar)
+// HOISTED: every block sweeps at most one tile (the iteration kernels' form,
+// chosen on the host so that each instantiation holds only one path).
+template <typename T, bool HOISTED>
+__global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsigned *bar)
 {
     if (a.skip && *a.skip) return;
     // the usual case: the captured kernels finished the solve
@@ -842,7 +967,12 @@ __global__ void __launch_bounds__(256) k_cg_tail(CgArgs<T> a, int it0, unsigned 
     unsigned gen = 0;
     bool ok = true;
     for (int it = it0;; ++it) {
-        if (cg_iteration<T>(a, it, nprev, s_c, s_beta, blockIdx.x, gridDim.x)) break;
+        bool done;
+        if constexpr (HOISTED)
+            done = cg_iter_hoisted<T>(a, it, nprev, s_c, s_beta, blockIdx.x);
+        else
+            done = cg_iteration<T>(a, it, nprev, s_c, s_beta, blockIdx.x, gridDim.x);
+        if (done) break;
         nprev = gridDim.x;
         ok = grid_barrier(bar, ++gen);
         if (!ok) break;
@@ -952,9 +1082,14 @@ int cg_tail_blocks()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_tail<T>, kTile, 0) != hipSuccess ||
-        per < 1)
+    int per_h = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg_tail<T, false>, kTile, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_h, k_cg_tail<T, true>, kTile, 0) !=
+            hipSuccess)
         return 0;
+    per = std::min(per, per_h);
+    if (per < 1) return 0;
     // at most two blocks per CU, a multiple of 8: all resident at once
     const int nb = (cus * std::min(per, 2)) & ~7;
     return std::min(nb, kMaxBlocks);
@@ -967,7 +1102,10 @@ hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st)
     // side inside a graph; co-residency holds because the grid fits the
     // device at once and stream order leaves it empty, and the bounded wait
     // of the barrier turns any violation into an error status
-    hipLaunchKernelGGL(k_cg_tail<T>, dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar);
+    if ((blocks >> 3) >= ((a.tiles + 7) >> 3))
+        hipLaunchKernelGGL((k_cg_tail<T, true>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar);
+    else
+        hipLaunchKernelGGL((k_cg_tail<T, false>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar);
     return hipGetLastError();
 }
 
