@@ -126,8 +126,13 @@ typedef struct {
     ec_solve_opts solve;
     /* PCG iteration kernels a captured graph issues per solve, for the
      * source and the coupling sequence; 0 = solve.maxit (at most 4096).
-     * A solve that needs more ends with EC_ERR_NOT_CONVERGED in its record
-     * and in the worst-status counter.  Eager calls ignore these. */
+     * With a smaller positive budget, an FP64 solve of a single problem that
+     * needs more iterations continues in one persistent kernel up to
+     * solve.maxit (same iterates: with at most one 256-node tile per block
+     * the results do not depend on the budget); an FP32-refined inner pass
+     * stops at the budget and the FP64 outer loop goes on.  A solve short of
+     * its tolerance at solve.maxit ends with EC_ERR_NOT_CONVERGED in its
+     * record and in the worst-status counter.  Eager calls ignore these. */
     int32_t graph_iters[2];
 } ec_step_opts;
 

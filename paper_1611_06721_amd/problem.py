@@ -263,9 +263,10 @@ class Graph:
 
 
 class Batch:
-    """Problems of uneven size stepped together (one launch per batched PCG
-    iteration).  All problems must share one stream: create them with
-    Problem(wl, stream=s) for a common torch stream s."""
+    """Problems of uneven size stepped together: every kernel of a step (PCG
+    iterations, start vectors, history pushes, the conducting update) is one
+    launch for all problems.  All problems must share one stream: create them
+    with Problem(wl, stream=s) for a common torch stream s."""
 
     def __init__(self, problems):
         self.problems = list(problems)
