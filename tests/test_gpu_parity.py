@@ -330,9 +330,10 @@ def test_trajectory_nonlinear16(ec, oracle_mod):
 def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
     """Captured steps replayed after eager warm-up steps: with iteration
     budgets that cover every solve the trajectory is bitwise the eager one;
-    with budgets far too small the persistent tail finishes the solves (same
-    iterates up to the order of the reductions); maxit still reports
-    NOT_CONVERGED."""
+    with budgets far too small the persistent tail finishes the solves, and
+    on these grids (at most one 256-node tile per block) it runs the same
+    iteration body as the captured kernels, so the trajectory is still
+    bitwise the eager one; maxit still reports NOT_CONVERGED."""
     G1, O, wl = pair(ec, oracle_mod, name)
     dt = 0.5 * 2 / O.power(iters=40)
     opts = ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10)
@@ -357,12 +358,8 @@ def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
         c = G2.counters()
         assert c["worst_status"] == 0 and c["steps"] == 20
         n_ref = int(its[20:].sum())
-        if budget == cover:
-            assert np.array_equal(got, ref)
-            assert c["iters_src"] + c["iters_cpl"] == n_ref
-        else:
-            assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
-            assert abs(c["iters_src"] + c["iters_cpl"] - n_ref) <= max(4, n_ref // 20)
+        assert np.array_equal(got, ref), budget
+        assert c["iters_src"] + c["iters_cpl"] == n_ref
         del g
     # maxit below the need: reported, not hidden (also through the tail)
     A3 = G2.zeros()
