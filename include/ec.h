@@ -331,7 +331,11 @@ int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt, int32_t che
  * ec_graph_launch.
  * ec_batch_set_tiles / ec_batch_autotune: the tiles of 256 nodes each block
  * of a batched iteration sweeps (1..64).  The autotuner times 1, 2, 4 and 8
- * on the batch itself and keeps the fastest; with cache_path it first looks
+ * on the batch itself, each as one iteration launch with every solve active
+ * and one with every solve finished, and keeps the one with the least
+ * active + 8 x finished time (a captured batch step issues several launches
+ * in which most solves have finished for each one in which all work);
+ * *us_per_iter is the active time of the pick.  With cache_path it first looks
  * for a pick recorded for this device and batch shape and appends new picks
  * (one text line each), so a cached batch always gets the same config.
  * Errors: EC_ERR_ARG / EC_ERR_STATE; the message is ec_last_error(NULL). */

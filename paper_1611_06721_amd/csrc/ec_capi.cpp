@@ -1708,6 +1708,7 @@ struct ec_batch_s {
     int *inst_d = nullptr, *off_d = nullptr, *flag_d = nullptr;
     int total_blocks = 0, max_blocks = 0;
     int tiles_per_block = 1;
+    bool one_tile = true;                          // every instance: one tile per block
 };
 
 static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_batch_s *b)
@@ -1777,6 +1778,9 @@ static int32_t batch_apply_tiles(ec_batch_s *b, int f)
     }
     b->total_blocks = (int)im.size();
     b->tiles_per_block = f;
+    b->one_tile = true;
+    for (ec_problem *h : b->inst)
+        if ((h->cg_blocks >> 3) < ((h->tiles + 7) >> 3)) b->one_tile = false;
     ec_problem *h0 = b->inst[0];
     HIP_TRY(h0, hipMemcpyAsync(b->inst_d, im.data(), im.size() * 4, hipMemcpyHostToDevice, b->st));
     HIP_TRY(h0, hipMemcpyAsync(b->off_d, of.data(), of.size() * 4, hipMemcpyHostToDevice, b->st));
@@ -1935,14 +1939,16 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
         int budget = std::min(maxit, kGraphMaxIters);
         if (o->graph_iters[s] > 0) budget = std::min(budget, o->graph_iters[s]);
         for (int it = 0; it < budget; ++it)
-            cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, it, b->st);
+            cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, it, b->one_tile,
+                          b->st);
         issued = budget;
     } else {
         int chunk = 8;
         while (issued < maxit) {
             const int c = std::min(chunk, maxit - issued);
             for (int j = 0; j < c; ++j)
-                cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, issued + j, b->st);
+                cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, issued + j,
+                              b->one_tile, b->st);
             issued += c;
             batch_done(b->tab_d[s], n, issued, b->flag_d, b->st);
             HIP_TRY(h0, hipMemcpyAsync(h0->pin + 20, b->flag_d, 4, hipMemcpyDeviceToHost, b->st));
@@ -2115,11 +2121,16 @@ extern "C" int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *
 
 // Average duration of one batched PCG iteration (every instance active) for
 // the current grids: zero-start solves of the sources into scratch vectors.
-static int32_t batch_time_iteration(ec_batch_s *b, double *us)
+// Time of one batched iteration launch: with every solve active (maxit
+// large), or with every solve finished (maxit 1: iteration 0 works, from
+// iteration 1 on every block leaves after its checks).
+constexpr double kBatchIdleWeight = 8.0;
+
+static int32_t batch_time_iteration(ec_batch_s *b, double *us, bool idle = false)
 {
     ec_solve_opts o{};
     o.rtol = 1e-300;
-    o.maxit = 1 << 30;
+    o.maxit = idle ? 1 : 1 << 30;
     std::vector<CgArgs<double>> t;
     for (ec_problem *h : b->inst) {
         CgArgs<double> a = cg64_args(h, EC_SEQ_USER, h->xs_d, &h->ctrl_d->one, h->t4, &o, nullptr);
@@ -2132,13 +2143,15 @@ static int32_t batch_time_iteration(ec_batch_s *b, double *us)
                                hipMemcpyHostToDevice, b->st));
     const int warm = 4, reps = 40;
     for (int it = 0; it < warm; ++it)
-        cg_iter_batch(b->tab_d[0], b->inst_d, b->off_d, b->total_blocks, it, b->st);
+        cg_iter_batch(b->tab_d[0], b->inst_d, b->off_d, b->total_blocks, it, b->one_tile,
+                      b->st);
     hipEvent_t e0, e1;
     HIP_TRY(h0, hipEventCreate(&e0));
     HIP_TRY(h0, hipEventCreate(&e1));
     HIP_TRY(h0, hipEventRecord(e0, b->st));
     for (int it = warm; it < warm + reps; ++it)
-        cg_iter_batch(b->tab_d[0], b->inst_d, b->off_d, b->total_blocks, it, b->st);
+        cg_iter_batch(b->tab_d[0], b->inst_d, b->off_d, b->total_blocks, it, b->one_tile,
+                      b->st);
     HIP_TRY(h0, hipEventRecord(e1, b->st));
     HIP_TRY(h0, hipEventSynchronize(e1));
     float ms = 0.0f;
@@ -2194,15 +2207,21 @@ extern "C" int32_t ec_batch_autotune(ec_batch b, const char *cache_path, int32_t
             }
         }
     }
+    // a captured batch step issues several launches in which most solves
+    // have already finished for each one in which they all work: the pick
+    // minimises active + kBatchIdleWeight x idle launch time
     int best_f = 1;
-    double best_us = 1e300;
+    double best_us = 1e300, best_cost = 1e300;
     for (int f : {1, 2, 4, 8}) {
         int32_t rc = batch_apply_tiles(b, f);
         if (rc) return rc;
-        double us = 0.0;
+        double us = 0.0, idle = 0.0;
         rc = batch_time_iteration(b, &us);
+        if (!rc) rc = batch_time_iteration(b, &idle, true);
         if (rc) return rc;
-        if (us < best_us) {
+        const double cost = us + kBatchIdleWeight * idle;
+        if (cost < best_cost) {
+            best_cost = cost;
             best_us = us;
             best_f = f;
         }

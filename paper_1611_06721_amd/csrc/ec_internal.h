@@ -186,7 +186,7 @@ template <typename T>
 void cg_fin(const CgArgs<T> &a, int iters, hipStream_t st);
 // batched iteration: all solves of a batch, one launch (block map inst/off)
 void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
-                   int it, hipStream_t st);
+                   int it, bool one_tile, hipStream_t st);
 // *flag (device int) = 1 if every solve of tab[0..n) finished before iteration it
 // init (in `mode`) / final record of every solve of a batch in one launch
 void cg_init_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,

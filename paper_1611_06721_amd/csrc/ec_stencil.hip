@@ -668,8 +668,12 @@ __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
 
 // One iteration of every solve of a batch in one launch: block b serves
 // instance inst[b] as its block b - off[inst] (each instance's slice starts
-// at a multiple of 8 and has tab[i].blocks blocks), running exactly the
-// single-instance iteration.
+// at a multiple of 8 and has tab[i].blocks blocks).  HOISTED (chosen on the
+// host when every instance has at most one tile per block) runs the body of
+// the single-instance kernel for that case, so each instance's iteration is
+// the same compiled arithmetic as when it is stepped alone; otherwise the
+// general body (one instantiation per path keeps the registers of each).
+template <bool HOISTED>
 __global__ void __launch_bounds__(256)
     k_cg_iter_batch(const CgArgs<double> *__restrict__ tab, const int *__restrict__ inst,
                     const int *__restrict__ off, int it)
@@ -683,14 +687,14 @@ __global__ void __launch_bounds__(256)
     }
     __shared__ CgCtl s_c;
     __shared__ double s_beta;
-    if (one_tile_per_block(a, a.blocks)) {
+    if constexpr (HOISTED) {
         cg_iter_hoisted<double>(a, it, a.blocks, s_c, s_beta, bid);
-        return;
+    } else {
+        double t[4];
+        part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, a.blocks, t);
+        if (cg_decide<double>(a, it, t, s_c, s_beta, bid)) return;
+        cg_update<double>(a, it, s_c, s_beta, bid, a.blocks);
     }
-    double t[4];
-    part_load(a.part + (int64_t)(it & 1) * 4 * kMaxBlocks, a.blocks, t);
-    if (cg_decide<double>(a, it, t, s_c, s_beta, bid)) return;
-    cg_update<double>(a, it, s_c, s_beta, bid, a.blocks);
 }
 
 // *flag = 1 if every solve of the batch has finished before iteration it
@@ -706,9 +710,14 @@ __global__ void k_batch_done(const CgArgs<double> *__restrict__ tab, int n, int 
 }
 
 void cg_iter_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
-                   int it, hipStream_t st)
+                   int it, bool one_tile, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_iter_batch, dim3(total_blocks), dim3(kTile), 0, st, tab, inst, off, it);
+    if (one_tile)
+        hipLaunchKernelGGL(k_cg_iter_batch<true>, dim3(total_blocks), dim3(kTile), 0, st, tab,
+                           inst, off, it);
+    else
+        hipLaunchKernelGGL(k_cg_iter_batch<false>, dim3(total_blocks), dim3(kTile), 0, st, tab,
+                           inst, off, it);
 }
 
 void cg_init_batch(const CgArgs<double> *tab, const int *inst, const int *off, int total_blocks,
