@@ -244,6 +244,10 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
         if mode == "batched_graph":
             graphs = [B.graph_capture(dts, As, gopts)]
         else:
+            # each problem alone on its own default PCG grid (the batch had
+            # set the grids of the handles it borrows)
+            for p in probs:
+                p.set_pcg_kernel(-1)
             graphs = [p.graph_capture(A, dt, gopts) for p, A, dt in zip(probs, As, dts)]
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -318,7 +318,10 @@ int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt, int32_t che
  *
  * ec_batch_sizes / ec_batch_create: n bound handles (all bound to the same
  * stream) and a caller-owned device workspace of ec_batch_sizes bytes
- * (256-byte aligned).  The batch borrows the handles (destroy it first).
+ * (256-byte aligned).  The batch borrows the handles (destroy it first) and
+ * sets the PCG iteration grid of each (its tiles per block, see
+ * ec_batch_set_tiles); ec_set_pcg_kernel(h, -1) gives a handle back its
+ * default grid for stepping alone.
  * ec_batch_step / ec_batch_run: dt[i] (host array) and A[i] (host array of
  * device state pointers) per instance; m < 0 (step) or m0 < 0 (run) takes
  * each instance's step index from its device counter.  Per-instance
