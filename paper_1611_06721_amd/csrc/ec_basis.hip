@@ -182,6 +182,7 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
             sq->a2 = 1.0;
             sq->ncol_md = good ? k : 0;
             sq->active = 1;
+            sq->push_on = 1;        // cleared by an FP64 solve that needs no iteration
         }
         break;
     }
@@ -196,7 +197,7 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
         if (tid == 0) {
             const double xx = val[k];
             sq->xnorm = sqrt(xx);
-            sq->active = (xx > 0.0 && xx <= 1e300) ? 1 : 0;
+            sq->active = (sq->push_on && xx > 0.0 && xx <= 1e300) ? 1 : 0;
             sq->a1 = 1.0;
             sq->slot_new = k;
             sq->ncol_md = k;
@@ -801,7 +802,7 @@ __global__ void k_seq_reset(SeqDev *sq)
         sq->k = 0; sq->w = 0; sq->kpod = 0; sq->head = 0; sq->count = 0;
         sq->accept = 0; sq->rotate = 0; sq->active = 0; sq->flags = 0; sq->zero_start = 1;
         sq->ncol_md = 0; sq->npush = 1; sq->slot_new = 0; sq->pod_info = 1.0; sq->rot_in = 0;
-        sq->rot_k = 0;
+        sq->rot_k = 0; sq->push_on = 1;
         for (int i = 0; i <= K; ++i) sq->s[i] = 1.0;
     }
 }
@@ -822,6 +823,13 @@ __global__ void k_seq_config(SeqDev *sq, int method, int cap, int kmax, double e
 void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st)
 {
     hipLaunchKernelGGL(k_seq_config, dim3(1), dim3(1), 0, st, seq, method, cap, kmax, eps);
+}
+
+__global__ void k_seq_push_on(SeqDev *sq) { sq->push_on = 1; }
+
+void seq_push_on(SeqDev *seq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seq_push_on, dim3(1), dim3(1), 0, st, seq);
 }
 
 }  // namespace ec

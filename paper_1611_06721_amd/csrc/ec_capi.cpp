@@ -658,6 +658,7 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
     a.m.a_extra = x;
     a.m.B[0] = {x, nullptr};
     a.m.nb = 1;
+    a.m.active = &sd->push_on;     // skipped after a solve that needed no iteration
     a.s1 = small_args(h, seq, OP_SPE_PUSH1, part);
     a.l1 = lc_args(h, seq, part);
     a.l1.v1 = x;
@@ -1117,6 +1118,7 @@ extern "C" int32_t ec_history_push(ec_handle h, int32_t seq, int32_t method, int
                            ? h->seq_eps[seq] : 1e-4;
     seq_ensure(h, seq, method, window, kmax, eps);
     seq_eta_ensure(h, seq, method, spe_eta(h, EC_PREC_FP64));
+    seq_push_on(h->seq_d + seq, h->st);
     seq_push(h, seq, method, x);
     return launch_check(h, "history push");
 }

@@ -67,7 +67,10 @@ struct SeqDev {
     double rot[kMaxWin * kMaxWin];              // basis rotation (SPE downdate)
     int rot_in, rot_k;                          // columns in / kept by the rotation
     int slot_new;                               // column slot being filled
-    int pad3;
+    // 0 when the last FP64 solve of the sequence needed no PCG iteration: its
+    // solution is the SPE start vector, which lies in span(q), so the
+    // dependency test of the next push rejects it; the push is skipped
+    int push_on;
 };
 
 // Per-handle control block in device memory.
@@ -151,7 +154,7 @@ struct CgArgs {
     const T *b;
     const double *bscale;    // device scalar multiplying b (nullptr: 1)
     int mode;                // START_*
-    const SeqDev *seq;       // START_DEV reads seq->zero_start; basis info
+    SeqDev *seq;       // START_DEV reads seq->zero_start; basis info
     double rtol;
     const double *rtol_dev;  // device tolerance read at the first iteration (nullptr: rtol)
     int maxit;
@@ -241,7 +244,7 @@ void lincomb_tab(const LcArgs *tab, int n, hipStream_t st);
 // in-place basis rotation: columns j < k' of A (and B) become sum_i rot[i,j] A_i
 struct RotArgs {
     double *A, *B;
-    const SeqDev *seq;
+    SeqDev *seq;
     int64_t ld, n;
 };
 void rotate(const RotArgs &r, hipStream_t st, const RotArgs *r1 = nullptr);
@@ -327,6 +330,8 @@ void refine_update(double *x, const float *d, const Ctrl *ctrl, int64_t n, hipSt
 void refine_final(double *x, const Ctrl *ctrl, int64_t n, hipStream_t st);
 void refine_reset(Ctrl *ctrl, hipStream_t st);
 void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st);
+// an explicit history push (not after a solve): the next push is not skipped
+void seq_push_on(SeqDev *seq, hipStream_t st);
 void negate(const double *x, double *y, int64_t n, hipStream_t st);
 
 // discrete adjoint of the time loop (ec_adjoint.hip); the *part launchers
