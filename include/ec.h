@@ -124,12 +124,13 @@ typedef struct {
     int32_t pod_kmax;
     double pod_eps;
     ec_solve_opts solve;
-    /* PCG iteration kernels a captured graph issues per solve, for the
-     * source and the coupling sequence; 0 = solve.maxit (at most 4096).
-     * With a smaller positive budget, an FP64 solve of a single problem that
-     * needs more iterations continues in one persistent kernel up to
-     * solve.maxit (same iterates: with at most one 256-node tile per block
-     * the results do not depend on the budget); an FP32-refined inner pass
+    /* PCG iterations a captured graph budgets per solve, for the source and
+     * the coupling sequence; 0 = solve.maxit (at most 4096).  With a
+     * smaller positive budget B, an FP64 solve of a single problem runs
+     * B - 1 iteration kernels and then one persistent kernel that takes the
+     * B-th iteration and any further ones up to solve.maxit (same iterates:
+     * with at most one 256-node tile per block the results do not depend on
+     * the budget); an FP32-refined inner pass
      * stops at the budget and the FP64 outer loop goes on.  A solve short of
      * its tolerance at solve.maxit ends with EC_ERR_NOT_CONVERGED in its
      * record and in the worst-status counter.  Eager calls ignore these. */

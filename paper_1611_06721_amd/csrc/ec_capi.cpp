@@ -745,12 +745,15 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
         const bool tail = hintable && want > 0 && want < maxit &&
                           std::is_same<T, double>::value && h->tail_blocks > 0;
         if (want > 0) budget = std::min(budget, want);
-        for (int i = 0; i < budget; ++i) cg_iter<T>(a, i, st);
+        // with the tail, it runs the last budgeted iteration itself (the same
+        // iteration body; one launch fewer when the solve is already done)
+        const int kernels = tail ? budget - 1 : budget;
+        for (int i = 0; i < kernels; ++i) cg_iter<T>(a, i, st);
         // rare long solves (cold start, a sudden change of the source) finish
         // in one persistent launch instead of failing at the budget
         if constexpr (std::is_same<T, double>::value) {
             if (tail) {
-                hipError_t e = cg_tail<double>(a, budget, h->tail_blocks, st);
+                hipError_t e = cg_tail<double>(a, kernels, h->tail_blocks, st);
                 if (e != hipSuccess)
                     return fail(h, EC_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
             }

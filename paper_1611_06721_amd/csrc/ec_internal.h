@@ -174,11 +174,13 @@ struct CgArgs {
     int t25, kb25, nti25, ntj25, ntk25;
 };
 
-// grid barrier of the persistent tail kernel: 8 release words, then one
-// arrival word per block, each kBarStride words apart (separate 128-byte
+// grid barrier of the persistent tail kernel: per-XCD population, arrival
+// and release words for up to kBarXcc XCDs, one counter and one release
+// word for the whole grid, each kBarStride words apart (separate 128-byte
 // lines); bounded waits
 constexpr int kBarStride = 32;
-constexpr int kBarWords = 8 + kMaxBlocks;
+constexpr int kBarXcc = 16;
+constexpr int kBarWords = 3 * kBarXcc + 2;
 constexpr long kSpinLimit = 1L << 22;
 
 template <typename T>

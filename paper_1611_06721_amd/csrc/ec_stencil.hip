@@ -895,57 +895,98 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Grid barrier of a launch whose blocks are all resident.  Every block posts
-// its arrival (the generation) in a word of its own; the threads of block 0
-// watch all arrival words together, then post the generation to eight release
-// words, and block b watches word b % 8.  Polls are relaxed loads from
-// separate 128-byte lines (no shared counter that every block updates or
-// polls); an agent-scope release fence before the arrival and an acquire
-// fence after the release publish the vectors and partials the blocks wrote.
+// Grid barrier of a launch whose blocks are all resident, grouped by the
+// XCD (accelerator complex die, one L2 each) a block runs on, read from the
+// hardware register.  A block's stores reach its XCD's L2 before it arrives
+// (a wait on its own memory counters in every wave); the last block of an
+// XCD to arrive writes back that whole L2 (an agent-scope release fence
+// operates on the cache, so it publishes every block of the XCD), meets the
+// other XCDs' last arrivers on one counter and releases its XCD; every block
+// then takes an agent-scope acquire fence.  One L2 write-back per XCD
+// instead of one per block, and no block polls more than one word.
+// Barrier words, kBarStride apart: pop[kBarXcc] (blocks per XCD, counted at
+// the first barrier of the launch), cnt[kBarXcc] (arrivals per XCD), top
+// (arrivals of the XCDs' last blocks), grel (global release), xrel[kBarXcc]
+// (release per XCD); all zero at launch.
 // Every wait is bounded: false if the spin limit was reached (never
-// expected); block 0 then posts no release and the other blocks time out too.
-__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen)
+// expected); a group whose release never comes then times out too.
+struct BarState {
+    unsigned x = 0, pop = 0, groups = 0;   // XCD, its blocks, XCDs in use
+};
+
+__device__ __forceinline__ unsigned xcd_id()
+{
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & (kBarXcc - 1);
+}
+
+__device__ __forceinline__ bool spin_until(const unsigned *w, unsigned target)
+{
+    long spins = 0;
+    while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > kSpinLimit) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen, BarState &bs)
 {
     __shared__ int s_ok;
-    unsigned *rel = bar, *arrive = bar + 8 * kBarStride;
+    // this wave's stores acknowledged by the L2
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(arrive + (int64_t)blockIdx.x * kBarStride, gen, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    int ok = 1;
-    if (blockIdx.x == 0) {
-        long spins = 0;
-        for (;;) {
-            int mine = 1;
-            for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
-                if (__hip_atomic_load(arrive + (int64_t)q * kBarStride, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT) < gen)
-                    mine = 0;
-            if (__syncthreads_and(mine)) break;
-            if (++spins > kSpinLimit) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (ok && threadIdx.x < 8) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            __hip_atomic_store(rel + threadIdx.x * kBarStride, gen, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-    if (threadIdx.x == 0) {
-        if (ok) {
-            const unsigned *w = rel + (blockIdx.x & 7) * kBarStride;
+        unsigned *pop = bar, *cnt = bar + kBarXcc * kBarStride;
+        unsigned *top = bar + 2 * kBarXcc * kBarStride, *grel = top + kBarStride;
+        unsigned *xrel = grel + kBarStride;
+        int ok = 1;
+        if (gen == 1) {
+            // population of each XCD: every block counts itself once
+            bs.x = xcd_id();
+            __hip_atomic_fetch_add(pop + bs.x * kBarStride, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             long spins = 0;
-            while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+            for (;;) {
+                unsigned tot = 0, groups = 0, mine = 0;
+                for (int q = 0; q < kBarXcc; ++q) {
+                    const unsigned v = __hip_atomic_load(pop + q * kBarStride, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    tot += v;
+                    groups += v > 0u;
+                    if (q == (int)bs.x) mine = v;
+                }
+                if (tot >= gridDim.x) {
+                    bs.pop = mine;
+                    bs.groups = groups;
+                    break;
+                }
                 if (++spins > kSpinLimit) {
                     ok = 0;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (ok) {
+            const unsigned old = __hip_atomic_fetch_add(cnt + bs.x * kBarStride, 1u,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 == gen * bs.pop) {
+                // last of its XCD: write the L2 back, then meet the others
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __builtin_amdgcn_s_waitcnt(0);
+                const unsigned t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (t + 1 == gen * bs.groups)
+                    __hip_atomic_store(grel, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    ok = spin_until(grel, gen);
+                if (ok)
+                    __hip_atomic_store(xrel + bs.x * kBarStride, gen, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = spin_until(xrel + bs.x * kBarStride, gen);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -958,7 +999,8 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen)
 // Finishes a solve that the captured iteration kernels left unfinished:
 // iterations it0, it0+1, ... in one persistent launch, a grid barrier
 // between iterations, until the (uniform) convergence / maxit decision.
-// Ends by storing the final record in both control slots.
+// Ends with the final record in slot (it0 + 1) & 1 (in both slots when it
+// took more than one iteration).
 // HOISTED: every block sweeps at most one tile (the iteration kernels' form,
 // chosen on the host so that each instantiation holds only one path).
 template <typename T, bool HOISTED>
@@ -974,8 +1016,10 @@ __global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsign
     __shared__ double s_beta;
     int nprev = a.blocks;
     unsigned gen = 0;
+    BarState bs;
     bool ok = true;
-    for (int it = it0;; ++it) {
+    int it = it0;
+    for (;; ++it) {
         bool done;
         if constexpr (HOISTED)
             done = cg_iter_hoisted<T>(a, it, nprev, s_c, s_beta, blockIdx.x);
@@ -983,11 +1027,14 @@ __global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsign
             done = cg_iteration<T>(a, it, nprev, s_c, s_beta, blockIdx.x, gridDim.x);
         if (done) break;
         nprev = gridDim.x;
-        ok = grid_barrier(bar, ++gen);
+        ok = grid_barrier(bar, ++gen, bs);
         if (!ok) break;
     }
+    // decided in its first iteration: that decision already stored the
+    // record in slot (it0 + 1) & 1, the one the final kernel reads
+    if (ok && it == it0) return;
     // every block has read the control slots of its last iteration
-    if (ok) ok = grid_barrier(bar, ++gen);
+    if (ok) ok = grid_barrier(bar, ++gen, bs);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         CgCtl f = s_c;
         if (!ok) {
