@@ -249,9 +249,14 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
         else:
             # each problem alone on its own default PCG grid (the batch had
             # set the grids of the handles it borrows)
+            # as chains: with 64 different graphs launched in turn, graphs
+            # whose history pushes fork onto a branch ran slower (2,128
+            # against 2,309 instance-steps/s on the same box)
             for p in probs:
                 p.set_pcg_kernel(-1)
-            graphs = [p.graph_capture(A, dt, gopts) for p, A, dt in zip(probs, As, dts)]
+            sopts = ec.step_opts(ec.SV_SPE, window=8, rtol=rtol, graph_iters=tuple(budgets),
+                                 graph_serial=True)
+            graphs = [p.graph_capture(A, dt, sopts) for p, A, dt in zip(probs, As, dts)]
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)

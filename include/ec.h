@@ -135,6 +135,12 @@ typedef struct {
      * its tolerance at solve.maxit ends with EC_ERR_NOT_CONVERGED in its
      * record and in the worst-status counter.  Eager calls ignore these. */
     int32_t graph_iters[2];
+    /* 1: a captured step runs as one chain of kernels.  0 (default): with an
+     * SPE or POD history and FP64 solves, the history pushes run on a forked
+     * branch beside the other sequence's work (see ec_graph_capture_step);
+     * a chain suits many different graphs launched in turn.  Eager calls
+     * ignore it. */
+    int32_t graph_serial;
 } ec_step_opts;
 
 /* Create a problem (host only): validates the descriptors, builds the edge
@@ -358,7 +364,19 @@ int32_t ec_batch_autotune(ec_batch b, const char *cache_path, int32_t *tiles_per
                           double *us_per_iter);
 
 /* HIP graph of one step (device step counter, fixed dt and opts) captured on
- * the bound stream; launch replays it on `hip_stream`. */
+ * the bound stream; launch replays it on `hip_stream` (the bound stream).
+ * With an SPE or POD history, FP64 solves and opts->graph_serial = 0 the
+ * graph forks: the history pushes run on a
+ * side stream of the library beside the other sequence's work (the previous
+ * step's coupling push beside the source start and solve, the source push
+ * beside the coupling start and solve), so a launch leaves its own coupling
+ * solution due for a push; the next launch makes it first, and every other
+ * call on the handle that reads or changes the histories, the solutions or
+ * what a push computes (solve, start vector, history calls, step, run,
+ * set_state, set_material, set_gauge_penalty, set_dependency_tol, tuning,
+ * adjoint and batch calls) makes it before its own work.  The results are
+ * those of eager steps.  A graph refers to the problem's buffers and state:
+ * destroy it before the problem; graph_exec is an opaque handle. */
 int32_t ec_graph_capture_step(ec_handle h, double dt, double *A, const ec_step_opts *opts,
                               ec_solve_info *dev_info, void **graph_exec);
 int32_t ec_graph_launch(void *graph_exec, void *hip_stream);

@@ -59,7 +59,8 @@ class SolveInfo(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("start_method", C.c_int32), ("window", C.c_int32), ("pod_kmax", C.c_int32),
-                ("pod_eps", C.c_double), ("solve", SolveOpts), ("graph_iters", C.c_int32 * 2)]
+                ("pod_eps", C.c_double), ("solve", SolveOpts), ("graph_iters", C.c_int32 * 2),
+                ("graph_serial", C.c_int32)]
 
 
 # every symbol the header declares, with its signature

@@ -34,9 +34,89 @@ constexpr int kMdWaves = kMdThreads / 64;
 // All threads of the block call these (uniform barriers); serial parts run
 // on thread 0, parallel loops stride over the block.
 
-// Cholesky solve H y = g (n x n, leading dimension K); false if H is not
-// numerically positive definite.
-__device__ bool chol_solve(const double *H, double *L, double *y, const double *gv, int n)
+// value of v in lane l (l the same in every lane): two scalar lane reads
+__device__ __forceinline__ double lane_read(double v, int l)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Cholesky solve H y = g (n x n, leading dimension K, n <= NM) by wave 0,
+// lane r holding row r of the factor in registers (no block barrier inside):
+// right-looking, column j scaled by the pivot's square root, then the
+// trailing lower triangle updated; forward substitution by columns,
+// backward by rows.  Sets *bad when a pivot is not positive relative to the
+// largest diagonal entry.  y: n values (shared memory).
+template <int NM>
+__device__ __forceinline__ void chol_wave(const double *H, double *y, const double *gv, int n,
+                                          int *bad_out)
+{
+    const int r = threadIdx.x;
+    double a[NM];
+#pragma unroll
+    for (int c = 0; c < NM; ++c) a[c] = (r < n && c <= r) ? H[r * K + c] : 0.0;
+    double gr = r < n ? gv[r] : 0.0;
+    double dg = 0.0;
+#pragma unroll
+    for (int c = 0; c < NM; ++c)
+        if (c == r) dg = a[c];
+    double dmax = r < n ? fabs(dg) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        if (j < n) {
+            const double d = lane_read(a[j], j);
+            if (!(d > 1e-14 * dmax)) bad = 1;
+            const double ljj = d > 0.0 ? sqrt(d) : 1.0;
+            if (r == j) a[j] = ljj;
+            else if (r > j) a[j] /= ljj;
+#pragma unroll
+            for (int c = j + 1; c < NM; ++c) {
+                if (c < n) {
+                    const double lcj = lane_read(a[j], c);
+                    if (r >= c) a[c] -= a[j] * lcj;
+                }
+            }
+        }
+    }
+    // L z = g: z_j leaves lane j, the rows below subtract L[r][j] z_j
+    double z[NM];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        z[j] = 0.0;
+        if (j < n) {
+            z[j] = lane_read(gr, j) / lane_read(a[j], j);
+            if (r > j) gr -= a[j] * z[j];
+        }
+    }
+    // L^T y = z, rows from the last: y_i = (z_i - sum_{j>i} L[j][i] y_j) / L[i][i]
+#pragma unroll
+    for (int i = NM - 1; i >= 0; --i) {
+        if (i < n) {
+            double t = z[i];
+#pragma unroll
+            for (int j = i + 1; j < NM; ++j)
+                if (j < n) t -= lane_read(a[i], j) * z[j];
+            z[i] = t / lane_read(a[i], i);
+        }
+    }
+    if (r == 0) {
+#pragma unroll
+        for (int c = 0; c < NM; ++c)
+            if (c < n) y[c] = z[c];
+        *bad_out = bad;
+    }
+}
+
+// The same factorisation for any n <= K with the factor in shared memory L
+// (leading dimension K), serial parts on thread 0, block barriers between
+// the steps.
+__device__ __noinline__ int chol_shared(const double *H, double *L, double *y, const double *gv,
+                                        int n)
 {
     __shared__ int s_bad;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -77,6 +157,20 @@ __device__ bool chol_solve(const double *H, double *L, double *y, const double *
             y[i] = s / L[i * K + i];
         }
     }
+    __syncthreads();
+    return s_bad;
+}
+
+// Cholesky solve H y = g (n x n, leading dimension K, n <= K); false if H is
+// not numerically positive definite.  All threads of the block call it.
+// Windows of up to kCholReg columns (the usual case) factor in registers on
+// wave 0; larger ones in shared memory L.
+constexpr int kCholReg = 12;
+__device__ bool chol_solve(const double *H, double *L, double *y, const double *gv, int n)
+{
+    __shared__ int s_bad;
+    if (n > kCholReg) return chol_shared(H, L, y, gv, n) == 0;
+    if (threadIdx.x < 64) chol_wave<kCholReg>(H, y, gv, n, &s_bad);
     __syncthreads();
     return s_bad == 0;
 }
@@ -182,7 +276,7 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
             sq->a2 = 1.0;
             sq->ncol_md = good ? k : 0;
             sq->active = 1;
-            sq->push_on = 1;        // cleared by an FP64 solve that needs no iteration
+            sq->push_on = 1;        // this solution is due for a push (see push_on)
         }
         break;
     }
@@ -318,8 +412,10 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
         break;
     }
     case OP_POD_PUSH: {
-        // new row/column of G = X^T X and H = X^T K X at the ring slot
-        if (tid == 0) {
+        // new row/column of G = X^T X and H = X^T K X at the ring slot (a
+        // push that is due: the push consumes the gate)
+        if (tid == 0 && sq->push_on) {
+            sq->push_on = 0;
             const int s = sq->slot_new, nc = sq->npush;
             for (int i = 0; i < nc; ++i) {
                 sq->G[i * K + s] = val[2 * i];
@@ -336,6 +432,7 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
     }
     case OP_POD_START: {
         const int n = sq->count;
+        if (tid == 0) sq->push_on = 1;      // this solution is due for a push
         if (n == 0) {
             if (tid == 0) {
                 sq->zero_start = 1; sq->kpod = 0; sq->pod_info = 1.0; sq->flags = 0;
@@ -699,8 +796,11 @@ __device__ __forceinline__ void rotate_body(const RotArgs &r)
 {
     double *A = r.A, *B = r.B;
     const int64_t ld = r.ld, n = r.n;
-    const SeqDev *seq = r.seq;
-    if (!seq->rotate) return;
+    SeqDev *seq = r.seq;
+    const int rot = seq->rotate;
+    // the last kernel of an SPE push: the pushed solution is no longer due
+    if (blockIdx.x == 0 && threadIdx.x == 0) seq->push_on = 0;
+    if (!rot) return;
     __shared__ double R[K * K];
     const int kin = seq->rot_in, kout = seq->rot_k;
     for (int t = threadIdx.x; t < K * K; t += blockDim.x) R[t] = seq->rot[t];
@@ -802,7 +902,7 @@ __global__ void k_seq_reset(SeqDev *sq)
         sq->k = 0; sq->w = 0; sq->kpod = 0; sq->head = 0; sq->count = 0;
         sq->accept = 0; sq->rotate = 0; sq->active = 0; sq->flags = 0; sq->zero_start = 1;
         sq->ncol_md = 0; sq->npush = 1; sq->slot_new = 0; sq->pod_info = 1.0; sq->rot_in = 0;
-        sq->rot_k = 0; sq->push_on = 1;
+        sq->rot_k = 0; sq->push_on = 0;
         for (int i = 0; i <= K; ++i) sq->s[i] = 1.0;
     }
 }

@@ -94,11 +94,21 @@ struct ec_problem {
     // host polling of the CG done flag (eager mode)
     int *pin = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // side stream of a captured step (the history pushes run on it) and the
+    // events that order it against the problem's stream
+    hipStream_t side = nullptr;
+    hipEvent_t sev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // start method of captured steps that were launched since the last
+    // flush: their last coupling solution may still be due for a push
+    int pending_meth = -1;
     ~ec_problem()
     {
         if (pin) (void)hipHostFree(pin);
         for (hipEvent_t &e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t &e : sev)
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -479,6 +489,10 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
     if (!h->pin) HIP_TRY(h, hipHostMalloc((void **)&h->pin, 128, hipHostMallocDefault));
     for (hipEvent_t &e : h->ev)
         if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipEvent_t &e : h->sev)
+        if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    h->pending_meth = -1;
     h->tiles = (int)((h->S + kTile - 1) / kTile);
     h->node_blocks = choose_blocks(h);
     h->cg_blocks = plan_25(h, false) ? h->grid25 : h->node_blocks;
@@ -642,8 +656,9 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
     double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
     PushArgs a{};
     if (method == EC_SV_POD) {
-        a.sa = SlotArgs{x, t3, KQ, Q, nullptr, &sd->slot_new, nullptr, 0.0};
+        a.sa = SlotArgs{x, t3, KQ, Q, nullptr, &sd->slot_new, &sd->push_on, 0.0};
         a.m = md_args(h, part);
+        a.m.active = &sd->push_on;      // only a solution that is due
         a.m.A = Q;
         a.m.kp = &sd->npush;
         a.m.B[0] = {x, nullptr};
@@ -658,7 +673,7 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
     a.m.a_extra = x;
     a.m.B[0] = {x, nullptr};
     a.m.nb = 1;
-    a.m.active = &sd->push_on;     // skipped after a solve that needed no iteration
+    a.m.active = &sd->push_on;     // only a solution that is due
     a.s1 = small_args(h, seq, OP_SPE_PUSH1, part);
     a.l1 = lc_args(h, seq, part);
     a.l1.v1 = x;
@@ -684,14 +699,15 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
 }
 
 // Append solution xs[i] to the history of sequence seqs[i] (n = 1 or 2
-// independent sequences of one problem, same method): every kernel of the
-// push is one launch for both, each with its own scratch and partials.
+// independent sequences of one problem, same method) on stream st: every
+// kernel of the push is one launch for both, each with its own scratch and
+// partials (sets set0, set0 + 1).  Each push is gated on its sequence's
+// push_on and clears it.
 static void seq_push_n(ec_problem *h, int n, const int *seqs, int method,
-                       const double *const *xs)
+                       const double *const *xs, hipStream_t st, int set0 = 0)
 {
-    hipStream_t st = h->st;
     PushArgs a[2];
-    for (int i = 0; i < n; ++i) a[i] = seq_push_args(h, seqs[i], method, xs[i], i);
+    for (int i = 0; i < n; ++i) a[i] = seq_push_args(h, seqs[i], method, xs[i], set0 + i);
     const PushArgs *b = n == 2 ? &a[1] : nullptr;
     if (method == EC_SV_POD) {
         spmv_slots(h->g, h->ld, a[0].sa, st, b ? &b->sa : nullptr);
@@ -714,8 +730,30 @@ static void seq_push_n(ec_problem *h, int n, const int *seqs, int method,
 // append solution x to the history of seq
 static void seq_push(ec_problem *h, int seq, int method, const double *x)
 {
-    seq_push_n(h, 1, &seq, method, &x);
+    seq_push_n(h, 1, &seq, method, &x, h->st);
 }
+
+// Push the last coupling solution of launched graph steps if it is still due
+// (they leave it for the next step's start); every call that reads or
+// changes the histories, the solution buffers or what a push computes
+// begins with this, so that pushes keep the order of eager steps.
+static bool flush_pending(ec_problem *h)
+{
+    const int meth = h->pending_meth;
+    h->pending_meth = -1;
+    if (meth != EC_SV_SPE && meth != EC_SV_POD) return false;
+    seq_push(h, EC_SEQ_CPL, meth, h->sc);
+    return true;
+}
+
+// An executable captured step; for a problem's step with a start-vector
+// history also the problem and the method (a launch leaves the step's
+// coupling solution due for a push).
+struct GraphBox {
+    hipGraphExec_t ex;
+    ec_problem *h;
+    int meth;
+};
 
 // ------------------------------------------------------------- solve
 static bool capturing(ec_problem *h)
@@ -953,6 +991,7 @@ extern "C" int32_t ec_solve(ec_handle h, int32_t seq, int32_t method, int32_t wi
                             ec_solve_info *dev_info)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
     if (!aligned(b) || !aligned(x) || !opts)
         return fail(h, EC_ERR_ARG, "b, x must be 16-byte aligned device pointers; opts required");
@@ -966,6 +1005,7 @@ extern "C" int32_t ec_solve(ec_handle h, int32_t seq, int32_t method, int32_t wi
 extern "C" int32_t ec_set_gauge_penalty(ec_handle h, double factor)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!(factor >= 0.0) || !std::isfinite(factor))
         return fail(h, EC_ERR_ARG, "factor must be finite and >= 0");
     // histories built with another weight start anew at their next use
@@ -1021,6 +1061,7 @@ extern "C" int32_t ec_tune_pcg(ec_handle h, const char *cache_path, int32_t *ti_
                                int32_t *kb_out, double *us_out)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     std::string sig;
     {
         hipDeviceProp_t prop{};
@@ -1093,6 +1134,7 @@ extern "C" int32_t ec_tune_pcg(ec_handle h, const char *cache_path, int32_t *ti_
 extern "C" int32_t ec_set_dependency_tol(ec_handle h, double tol)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, EC_ERR_ARG, "tol must be in (0, 1)");
     h->dep_tol = tol;
     return EC_OK;
@@ -1101,6 +1143,7 @@ extern "C" int32_t ec_set_dependency_tol(ec_handle h, double tol)
 extern "C" int32_t ec_history_reset(ec_handle h, int32_t seq)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
     seq_reset(h->seq_d + seq, h->st);
     return launch_check(h, "history reset");
@@ -1110,6 +1153,7 @@ extern "C" int32_t ec_history_push(ec_handle h, int32_t seq, int32_t method, int
                                    const double *x)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
     if (method != EC_SV_SPE && method != EC_SV_POD)
         return fail(h, EC_ERR_ARG, "history push needs SPE or POD");
@@ -1131,6 +1175,7 @@ extern "C" int32_t ec_start_vector(ec_handle h, int32_t seq, int32_t method, int
                                    ec_solve_info *dev_info)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!valid_seq(seq)) return fail(h, EC_ERR_ARG, "seq must be 0..%d", EC_NSEQ - 1);
     if (method != EC_SV_SPE && method != EC_SV_POD)
         return fail(h, EC_ERR_ARG, "start vector needs SPE or POD");
@@ -1176,30 +1221,60 @@ extern "C" int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y)
 }
 
 // -------------------------------------------------------------- step
+// One explicit Euler step: source solve, coupled right-hand side, coupling
+// solve, history pushes, state update.  split (a captured step with a
+// start-vector history): the pushes run on the side stream beside the other
+// sequence's work, each on the second scratch set.  First the push of the
+// previous step's coupling solution (skipped when it was already made, see
+// SeqDev::push_on) beside this step's source start and solve, then this
+// step's source push beside the coupling start and solve; this step's
+// coupling solution stays due for the next step or a flush.  The pushes read
+// only their sequence's state and solution, so the results are those of the
+// eager order.
 static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const ec_step_opts *o,
-                         ec_solve_info *info)
+                         ec_solve_info *info, bool split = false)
 {
-    hipStream_t st = h->st;
-    step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st);
+    hipStream_t st = h->st, sd = h->side;
     const int meth = o->start_method;
+    split = split && (meth == EC_SV_SPE || meth == EC_SV_POD);
+    if (split) {
+        const int seq = EC_SEQ_CPL;
+        const double *x = h->sc;
+        HIP_TRY(h, hipEventRecord(h->sev[0], st));
+        HIP_TRY(h, hipStreamWaitEvent(sd, h->sev[0], 0));
+        seq_push_n(h, 1, &seq, meth, &x, sd, 1);
+        HIP_TRY(h, hipEventRecord(h->sev[1], sd));
+    }
+    step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st);
     int32_t rc = do_solve(h, EC_SEQ_SRC, meth, o->window, o->pod_kmax, o->pod_eps, h->xs_d,
                           &h->ctrl_d->scale, h->sj, &o->solve, info, false);
     if (rc) return rc;
+    if (split) {
+        const int seq = EC_SEQ_SRC;
+        const double *x = h->sj;
+        HIP_TRY(h, hipEventRecord(h->sev[2], st));
+        HIP_TRY(h, hipStreamWaitEvent(sd, h->sev[2], 0));
+        seq_push_n(h, 1, &seq, meth, &x, sd, 1);
+        HIP_TRY(h, hipEventRecord(h->sev[3], sd));
+    }
     UpdArgs u{};
     u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
     u.nc = h->nc; u.A = A; u.sj = h->sj; u.sc = h->sc; u.out = h->ac; u.dt = dt; u.apply = 0;
     u.ctrl = h->ctrl_d;
     update_c(u, st);
     if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
+    if (split) HIP_TRY(h, hipStreamWaitEvent(st, h->sev[1], 0));
     rc = do_solve(h, EC_SEQ_CPL, meth, o->window, o->pod_kmax, o->pod_eps, h->bcpl, nullptr, h->sc,
                   &o->solve, info ? info + 1 : nullptr, false);
     if (rc) return rc;
-    // both histories grow in the same launches: the source history is next
-    // read by the source solve of the following step
-    if (meth == EC_SV_SPE || meth == EC_SV_POD) {
+    if (split) {
+        HIP_TRY(h, hipStreamWaitEvent(st, h->sev[3], 0));
+    } else if (meth == EC_SV_SPE || meth == EC_SV_POD) {
+        // both histories grow in the same launches: the source history is
+        // next read by the source solve of the following step
         const int seqs[2] = {EC_SEQ_SRC, EC_SEQ_CPL};
         const double *xs[2] = {h->sj, h->sc};
-        seq_push_n(h, 2, seqs, meth, xs);
+        seq_push_n(h, 2, seqs, meth, xs, st);
     }
     finish_state(h->g, A, h->ac, h->sj, h->sc, h->ctrl_d, 1, st);
     return launch_check(h, "step");
@@ -1222,6 +1297,7 @@ extern "C" int32_t ec_step(ec_handle h, int64_t m, double dt, double *A, const e
                            ec_solve_info *dev_info)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     int32_t rc = check_step_args(h, dt, A, opts);
     if (rc) return rc;
     return step_impl(h, m, dt, A, opts, dev_info);
@@ -1231,6 +1307,7 @@ extern "C" int32_t ec_run(ec_handle h, int64_t m0, int64_t nsteps, double dt, do
                           const ec_step_opts *opts, ec_solve_info *dev_info)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     int32_t rc = check_step_args(h, dt, A, opts);
     if (rc) return rc;
     if (nsteps < 0) return fail(h, EC_ERR_ARG, "nsteps must be >= 0");
@@ -1246,6 +1323,7 @@ static int32_t set_state_impl(ec_problem *h, const double *A, const ec_solve_opt
 extern "C" int32_t ec_set_state(ec_handle h, const double *A, const ec_solve_opts *opts)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (!aligned(A) || !opts) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
     return set_state_impl(h, A, opts);
 }
@@ -1397,6 +1475,7 @@ static void conductivities(ec_problem *h, const int *mat_filter, std::vector<dou
 extern "C" int32_t ec_set_material(ec_handle h, int32_t mat_id, const ec_material *m)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     if (mat_id < 1 || mat_id >= h->mats.n || !m)
         return fail(h, EC_ERR_ARG, "mat_id must be 1..%d", h->mats.n - 1);
     if (!(m->sigma > 0) || !std::isfinite(m->sigma) || !(m->k1 >= 0) || !std::isfinite(m->k1) ||
@@ -1546,6 +1625,7 @@ extern "C" int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt,
                                       void *adj_ws, int64_t adj_bytes, double *A, double *loss)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     AdjWs w;
     int32_t rc = adj_args(h, n_steps, dt, checkpoint_every, opts, adj_ws, adj_bytes, A, &w);
     if (rc) return rc;
@@ -1588,6 +1668,7 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
                                        double *grads)
 {
     NEED_BOUND(h);
+    flush_pending(h);
     AdjWs w;
     int32_t rc = adj_args(h, n_steps, dt, checkpoint_every, opts, adj_ws, adj_bytes, nullptr, &w);
     if (rc) return rc;
@@ -2001,6 +2082,15 @@ static int32_t batch_step_impl(ec_batch_s *b, int64_t m, const double *dt, doubl
     return launch_check(b->inst[0], "batch step");
 }
 
+// pushes still due from launched graph steps of the instances (on their own
+// streams, finished before the batch's work)
+static int32_t batch_flush(ec_batch_s *b)
+{
+    for (ec_problem *h : b->inst)
+        if (flush_pending(h)) HIP_TRY(h, hipStreamSynchronize(h->st));
+    return EC_OK;
+}
+
 static int32_t batch_check(ec_batch_s *b, const double *dt, double *const *A,
                            const ec_step_opts *o)
 {
@@ -2014,7 +2104,7 @@ static int32_t batch_check(ec_batch_s *b, const double *dt, double *const *A,
         int32_t rc = check_step_args(b->inst[i], dt[i], A[i], o);
         if (rc) return fail(nullptr, rc, "instance %zu: %s", i, b->inst[i]->err.c_str());
     }
-    return EC_OK;
+    return batch_flush(b);
 }
 
 extern "C" int32_t ec_batch_sizes(int32_t n, const ec_handle *handles, int64_t *bytes)
@@ -2120,7 +2210,7 @@ extern "C" int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
-    *graph_exec = (void *)ex;
+    *graph_exec = (void *)new GraphBox{ex, nullptr, -1};
     return EC_OK;
 }
 
@@ -2254,6 +2344,7 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     if (!graph_exec) return fail(h, EC_ERR_ARG, "graph_exec is NULL");
     if (opts->graph_iters[0] < 0 || opts->graph_iters[1] < 0)
         return fail(h, EC_ERR_ARG, "graph_iters must be >= 0");
+    flush_pending(h);
     // configure the histories eagerly so that no reset is recorded
     for (int s : {EC_SEQ_SRC, EC_SEQ_CPL}) {
         seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
@@ -2264,7 +2355,10 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     HIP_TRY(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
     h->graph_iters[EC_SEQ_SRC] = opts->graph_iters[0];
     h->graph_iters[EC_SEQ_CPL] = opts->graph_iters[1];
-    rc = step_impl(h, -1, dt, A, opts, dev_info);
+    // the pushes on a branch of their own, except for a chain on request or
+    // FP32-refined solves (measured slower forked)
+    const bool fork = !opts->graph_serial && opts->solve.precision == EC_PREC_FP64;
+    rc = step_impl(h, -1, dt, A, opts, dev_info, fork);
     h->graph_iters[EC_SEQ_SRC] = h->graph_iters[EC_SEQ_CPL] = 0;
     hipError_t e = hipStreamEndCapture(h->st, &graph);
     if (rc) {
@@ -2276,21 +2370,29 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(h, EC_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
-    *graph_exec = (void *)ex;
+    const int meth = opts->start_method;
+    const bool due = fork && (meth == EC_SV_SPE || meth == EC_SV_POD);
+    *graph_exec = (void *)new GraphBox{ex, due ? h : nullptr, meth};
     return EC_OK;
 }
 
 extern "C" int32_t ec_graph_launch(void *graph_exec, void *hip_stream)
 {
     if (!graph_exec) return fail(nullptr, EC_ERR_ARG, "graph_exec is NULL");
-    hipError_t e = hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)hip_stream);
+    GraphBox *g = (GraphBox *)graph_exec;
+    hipError_t e = hipGraphLaunch(g->ex, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    if (g->h) g->h->pending_meth = g->meth;
     return EC_OK;
 }
 
 extern "C" int32_t ec_graph_destroy(void *graph_exec)
 {
-    if (graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+    if (graph_exec) {
+        GraphBox *g = (GraphBox *)graph_exec;
+        (void)hipGraphExecDestroy(g->ex);
+        delete g;
+    }
     return EC_OK;
 }
 

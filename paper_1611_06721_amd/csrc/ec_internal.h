@@ -67,9 +67,13 @@ struct SeqDev {
     double rot[kMaxWin * kMaxWin];              // basis rotation (SPE downdate)
     int rot_in, rot_k;                          // columns in / kept by the rotation
     int slot_new;                               // column slot being filled
-    // 0 when the last FP64 solve of the sequence needed no PCG iteration: its
-    // solution is the SPE start vector, which lies in span(q), so the
-    // dependency test of the next push rejects it; the push is skipped
+    // 1 while the solution of the sequence's last start is due for a push:
+    // set by the start, cleared by the last kernel of the push (so a push
+    // that was already made is skipped when it is issued again, as by a
+    // graph replay that pushes the previous step's solution), and for SPE
+    // also by an FP64 solve that needed no PCG iteration (its solution is the
+    // start vector, which lies in span(q), so the dependency test of the
+    // push would reject it); the push kernels are gated on it
     int push_on;
 };
 

@@ -1061,9 +1061,9 @@ __device__ __forceinline__ void cg_fin_body(const CgArgs<T> &a, int iters)
     int st = c.status;
     if (!c.done) st = EC_ERR_NOT_CONVERGED;
     const int it = c.it;
-    // an FP64 solve of a sequence that ended on its start vector: the next
-    // SPE push of this solution is a rejected one, skip its work
-    if (a.seq && !a.accum && it == 0) a.seq->push_on = 0;
+    // an FP64 solve of an SPE sequence that ended on its start vector: the
+    // push of this solution is a rejected one, skip its work
+    if (a.seq && !a.accum && it == 0 && a.seq->method == EC_SV_SPE) a.seq->push_on = 0;
     if (a.info) {
         if (a.accum) {
             a.info->iters += it;

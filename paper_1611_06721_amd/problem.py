@@ -29,12 +29,13 @@ def solve_opts(rtol=1e-8, maxit=100000, precision=L.PREC_FP64, inner_rtol=1e-5,
 
 
 def step_opts(method=L.SV_SPE, window=8, pod_kmax=None, pod_eps=1e-4, graph_iters=(0, 0),
-              **solve):
-    """graph_iters: PCG iteration kernels per solve (source, coupling) in a
-    captured step; 0 = maxit."""
+              graph_serial=False, **solve):
+    """graph_iters: PCG iterations budgeted per solve (source, coupling) in a
+    captured step; 0 = maxit.  graph_serial: capture the step as one chain
+    (no branch for the history pushes)."""
     kmax = window if pod_kmax is None else pod_kmax
     return L.StepOpts(method, window, kmax, pod_eps, solve_opts(**solve),
-                      (C.c_int32 * 2)(*graph_iters))
+                      (C.c_int32 * 2)(*graph_iters), 1 if graph_serial else 0)
 
 
 def info_array(info_tensor):

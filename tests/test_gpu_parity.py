@@ -333,7 +333,10 @@ def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
     with budgets far too small the persistent tail finishes the solves, and
     on these grids (at most one 256-node tile per block) it runs the same
     iteration body as the captured kernels, so the trajectory is still
-    bitwise the eager one; maxit still reports NOT_CONVERGED."""
+    bitwise the eager one; history pushes that a captured step runs beside
+    the other sequence's work (and the one it leaves due) keep the eager
+    order, so eager steps after the replays continue the eager trajectory
+    bitwise; maxit still reports NOT_CONVERGED."""
     G1, O, wl = pair(ec, oracle_mod, name)
     dt = 0.5 * 2 / O.power(iters=40)
     opts = ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10)
@@ -343,15 +346,17 @@ def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
     G1.run(A1, 0, 30, dt, opts, info=info1)
     its = ec.info_array(info1)["iters"]
     ref = A1.cpu().numpy()
+    G1.run(A1, 30, 5, dt, opts)
+    ref35 = A1.cpu().numpy()
     cover = (int(its[20::2].max()) + 2, int(its[21::2].max()) + 2)
-    for budget in (cover, (1, 2)):
+    for budget, serial in ((cover, False), ((1, 2), False), (cover, True)):
         G2 = ec.Problem(wl, window_cap=8)
         A2 = G2.zeros()
         G2.set_state(A2, rtol=1e-10)
         G2.run(A2, 0, 10, dt, opts)
         G2.counters_reset()
         g = G2.graph_capture(A2, dt, ec.step_opts(method, window=8, pod_kmax=6, rtol=1e-10,
-                                                  graph_iters=budget))
+                                                  graph_iters=budget, graph_serial=serial))
         for _ in range(20):
             g.launch()
         got = A2.cpu().numpy()
@@ -360,6 +365,11 @@ def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
         n_ref = int(its[20:].sum())
         assert np.array_equal(got, ref), budget
         assert c["iters_src"] + c["iters_cpl"] == n_ref
+        # a replay leaves its coupling solution due for a push (made beside
+        # the next step's source solve); eager steps after replays make it
+        # first, so the run continues as the eager one
+        G2.run(A2, 30, 5, dt, opts)
+        assert np.array_equal(A2.cpu().numpy(), ref35), budget
         del g
     # maxit below the need: reported, not hidden (also through the tail)
     A3 = G2.zeros()
