@@ -695,6 +695,9 @@ void multidot_tab(const MdArgs *tab, int n, hipStream_t st)
 // y1 = a1 v1 + sum_{i<k} cA_i A_i        (y1 may be column *slot of A)
 // y2 = a2 s2 v2 + sum_{i<k} cB_i B_i
 // partials: [0..k) A_i^T y1 (want_dots), then |y1|^2, |y2|^2, |s2 v2|^2
+// DOTS = a.want_dots, chosen on the host: the kernel without the dots does
+// not carry their registers.
+template <bool DOTS>
 __device__ __forceinline__ void lincomb_body(const LcArgs &a)
 {
     if (a.active && !*a.active) return;
@@ -734,15 +737,16 @@ __device__ __forceinline__ void lincomb_body(const LcArgs &a)
             n2 += u * u;
             nbb += bv * bv;
         }
-        if (a.want_dots) {
-            // second sweep over the same rows (cache hits): A_i^T y1
+        if constexpr (DOTS) {
+            // second sweep over the same rows (cache hits): A_i^T y1 (holding
+            // the row's entries in registers instead spilled and was slower)
 #pragma unroll
             for (int i = 0; i < KC; ++i)
                 if (i < k) dots[i] += a.A[(int64_t)i * a.ld + row] * v;
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nv = a.want_dots ? k : 0;
+    const int nv = DOTS ? k : 0;
 #pragma unroll
     for (int i = 0; i < KC; ++i) {
         if (i < nv) {
@@ -769,29 +773,48 @@ __device__ __forceinline__ void lincomb_body(const LcArgs &a)
     }
 }
 
-__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcArgs set0, LcArgs set1)
+// the two argument sets as one array in the kernel arguments: block row y
+// reads set y at a run-time offset (not both sets loaded and selected)
+struct LcPair {
+    LcArgs s[2];
+};
+
+template <bool DOTS>
+__global__ void __launch_bounds__(kMdThreads) k_lincomb(LcPair sets)
 {
-    lincomb_body(blockIdx.y ? set1 : set0);
+    lincomb_body<DOTS>(sets.s[blockIdx.y]);
 }
 
+template <bool DOTS>
 __global__ void __launch_bounds__(kMdThreads) k_lincomb_tab(const LcArgs *tab)
 {
-    lincomb_body(tab[blockIdx.y]);
+    lincomb_body<DOTS>(tab[blockIdx.y]);
 }
 
+// both sets (and every table row) have the same want_dots
 void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1)
 {
-    hipLaunchKernelGGL(k_lincomb, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st, a,
-                       a1 ? *a1 : a);
+    const LcPair sets{{a, a1 ? *a1 : a}};
+    if (a.want_dots)
+        hipLaunchKernelGGL(k_lincomb<true>, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st,
+                           sets);
+    else
+        hipLaunchKernelGGL(k_lincomb<false>, dim3(kMdBlocks, a1 ? 2 : 1), dim3(kMdThreads), 0, st,
+                           sets);
 }
 
-void lincomb_tab(const LcArgs *tab, int n, hipStream_t st)
+void lincomb_tab(const LcArgs *tab, int n, bool dots, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_lincomb_tab, dim3(kMdBlocks, n), dim3(kMdThreads), 0, st, tab);
+    if (dots)
+        hipLaunchKernelGGL(k_lincomb_tab<true>, dim3(kMdBlocks, n), dim3(kMdThreads), 0, st, tab);
+    else
+        hipLaunchKernelGGL(k_lincomb_tab<false>, dim3(kMdBlocks, n), dim3(kMdThreads), 0, st, tab);
 }
 
 // In-place rotation of the first rot_in columns of A (and B) into rot_k
-// columns: A'_j = sum_i rot[i][j] A_i.
+// columns: A'_j = sum_i rot[i][j] A_i.  One sweep over the rows for both
+// matrices: every row's inputs of A and B are loaded together and each
+// coefficient read from shared memory serves both.
 __device__ __forceinline__ void rotate_body(const RotArgs &r)
 {
     double *A = r.A, *B = r.B;
@@ -807,19 +830,29 @@ __device__ __forceinline__ void rotate_body(const RotArgs &r)
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n; row += stride) {
-#pragma unroll 1
-        for (int pass = 0; pass < 2; ++pass) {
-            double *M = pass == 0 ? A : B;
-            double v[KC];
+        double va[KC], vb[KC];
 #pragma unroll
-            for (int i = 0; i < KC; ++i) v[i] = i < kin ? M[(int64_t)i * ld + row] : 0.0;
-#pragma unroll 1
-            for (int j = 0; j < kout; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < KC; ++i) s += R[i * K + j] * v[i];
-                M[(int64_t)j * ld + row] = s;
+        for (int i = 0; i < KC; ++i) {
+            va[i] = 0.0;
+            vb[i] = 0.0;
+            if (i < kin) {
+                va[i] = A[(int64_t)i * ld + row];
+                vb[i] = B[(int64_t)i * ld + row];
             }
+        }
+#pragma unroll 1
+        for (int j = 0; j < kout; ++j) {
+            double sa = 0.0, sb = 0.0;
+#pragma unroll
+            for (int i = 0; i < KC; ++i) {
+                if (i < kin) {
+                    const double c = R[i * K + j];
+                    sa += c * va[i];
+                    sb += c * vb[i];
+                }
+            }
+            A[(int64_t)j * ld + row] = sa;
+            B[(int64_t)j * ld + row] = sb;
         }
     }
 }

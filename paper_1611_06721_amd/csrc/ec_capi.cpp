@@ -2009,7 +2009,7 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
     if (basis) {                 // start vectors of all instances (eqs. 10, 14)
         multidot_tab(t.m_start, n, b->st);
         small_tab(t.s_start, n, b->st);
-        lincomb_tab(t.l_start, n, b->st);
+        lincomb_tab(t.l_start, n, false, b->st);
     }
     // PCG inits of all instances (same start method, so the same mode)
     if (modes[0] == START_X) {
@@ -2051,9 +2051,9 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
     } else if (meth == EC_SV_SPE) {
         multidot_tab(t.m, n, b->st);
         small_tab(t.s1, n, b->st);
-        lincomb_tab(t.l1, n, b->st);
+        lincomb_tab(t.l1, n, true, b->st);
         small_tab(t.s2, n, b->st);
-        lincomb_tab(t.l2, n, b->st);
+        lincomb_tab(t.l2, n, false, b->st);
         small_tab(t.s3, n, b->st);
         spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
         multidot_tab(t.m2, n, b->st);

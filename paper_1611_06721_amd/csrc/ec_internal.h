@@ -245,7 +245,7 @@ struct LcArgs {
     int64_t n;
 };
 void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1 = nullptr);
-void lincomb_tab(const LcArgs *tab, int n, hipStream_t st);
+void lincomb_tab(const LcArgs *tab, int n, bool dots, hipStream_t st);
 
 // in-place basis rotation: columns j < k' of A (and B) become sum_i rot[i,j] A_i
 struct RotArgs {
