@@ -13,8 +13,10 @@
 // and at most kmax modes; eq. (13) is reported; x0 from eq. (14).
 //
 // The tall-skinny products run on the FP64 matrix cores and leave one row of
-// partial sums per block; a one-block kernel reduces the rows in a fixed
-// order and performs the small dense step of the sequence (OP_* codes).
+// partial sums per block; the small dense step of the sequence (OP_* codes)
+// that follows reduces the rows in a fixed order, in a one-block kernel or,
+// for the coefficient steps of a push, in every block of the kernel that
+// applies the coefficients.
 #include <math.h>
 
 #include "ec_device.h"
@@ -280,51 +282,6 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
         }
         break;
     }
-    case OP_SPE_PUSH1: {
-        // c1 = q^T x; w = x - q c1
-        for (int i = tid; i < K; i += nt) {
-            const double si = i < k ? sq->s[i] : 0.0;
-            const double c1 = si * (i < k ? val[i] : 0.0);
-            sq->c1[i] = c1;
-            sq->cA[i] = -c1 * si;
-        }
-        if (tid == 0) {
-            const double xx = val[k];
-            sq->xnorm = sqrt(xx);
-            sq->active = (sq->push_on && xx > 0.0 && xx <= 1e300) ? 1 : 0;
-            sq->a1 = 1.0;
-            sq->slot_new = k;
-            sq->ncol_md = k;
-            sq->accept = 0;     // set by OP_SPE_PUSH3 for an accepted column
-            sq->rotate = 0;     // set by OP_SPE_PUSH4 when the window slides
-        }
-        break;
-    }
-    case OP_SPE_PUSH2: {
-        // second pass: c2 = q^T w; x2 = w - q c2
-        for (int i = tid; i < K; i += nt) {
-            const double si = i < k ? sq->s[i] : 0.0;
-            const double c2 = si * (i < k ? val[i] : 0.0);
-            sq->c2[i] = c2;
-            sq->cA[i] = -c2 * si;
-        }
-        if (tid == 0) sq->a1 = 1.0;
-        break;
-    }
-    case OP_SPE_PUSH3: {
-        // accept x2 if it is not (numerically) in span(q): a linearly
-        // independent new column
-        if (tid == 0) {
-            const double rho = sqrt(val[0]);
-            sq->rho = rho;
-            const int acc = (sq->active && rho > tol * sq->xnorm && k + 1 < K) ? 1 : 0;
-            sq->accept = acc;
-            sq->active = acc;
-            if (acc) sq->s[k] = 1.0 / rho;
-            sq->ncol_md = k + 1;
-        }
-        break;
-    }
     case OP_SPE_PUSH4: {
         // new row/column of H = q^T K q and of the window coordinates R
         const int acc = sq->accept;
@@ -538,31 +495,6 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
     __syncthreads();
 }
 
-// Deterministic reduction of nvals values over the kMdBlocks block partials
-// (stored value-major: part[q * kMdBlocks + block]) into the shared val[]
-// (all threads of the block, blockDim.x = kMdBlocks = 256): every value's
-// partials are one coalesced load per wave, then a fixed-order wave butterfly
-// and a fixed-order sum of the four waves.
-__device__ void reduce_rows(const double *part, int nvals, double *val)
-{
-    __shared__ double tmp[kMdStride][4];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    double r[kMdStride];
-#pragma unroll
-    for (int q = 0; q < kMdStride; ++q)
-        r[q] = (q < nvals && tid < kMdBlocks) ? part[(int64_t)q * kMdBlocks + tid] : 0.0;
-#pragma unroll
-    for (int q = 0; q < kMdStride; ++q) {
-        if (q < nvals) {
-            const double sq = wave_sum(r[q]);
-            if (lane == 0) tmp[q][wv] = sq;
-        }
-    }
-    __syncthreads();
-    if (tid < nvals) val[tid] = ((tmp[tid][0] + tmp[tid][1]) + tmp[tid][2]) + tmp[tid][3];
-    __syncthreads();
-}
-
 // -------------------------------------------------------- basis products
 // part[(i*nb + j) * kMdBlocks + block] = sum over the block's rows of A_i B_j for p = k (+1 with
 // a_extra) columns of A and nb <= 4 vectors B.  One wave handles 16 rows per
@@ -697,21 +629,82 @@ void multidot_tab(const MdArgs *tab, int n, hipStream_t st)
 // partials: [0..k) A_i^T y1 (want_dots), then |y1|^2, |y2|^2, |s2 v2|^2
 // DOTS = a.want_dots, chosen on the host: the kernel without the dots does
 // not carry their registers.
+// The dense step OP_SPE_PUSH1 (c1 = q^T x, w = x - q c1, gate: a push that
+// is due and a finite nonzero x) or OP_SPE_PUSH2 (c2 = q^T w, x2 = w - q c2)
+// run by every block of the combination that applies it, on the reduced
+// partials of the preceding product: the block's coefficients into sA, the
+// gate into *gate, k into *kout.  Block 0 stores what the step stores; the
+// other blocks read only fields that no block of this launch writes.
+__device__ __forceinline__ void push_coef(SeqDev *sq, int op, const double *pin, double *sA,
+                                          int *gate, int *kout)
+{
+    __shared__ double val[kMaxWin];
+    const int k = sq->k;
+    int nv = op == OP_SPE_PUSH1 ? k + 1 : sq->ncol_md + 3;
+    nv = nv < 0 ? 0 : (nv > kMaxWin ? kMaxWin : nv);
+    reduce_rows<kMaxWin>(pin, nv, val);
+    const bool b0 = blockIdx.x == 0;
+    if (threadIdx.x < K) {
+        const int i = threadIdx.x;
+        const double si = i < k ? sq->s[i] : 0.0;
+        const double c = si * (i < k ? val[i] : 0.0);
+        sA[i] = i < k ? -c * si : 0.0;
+        if (b0) {
+            (op == OP_SPE_PUSH1 ? sq->c1 : sq->c2)[i] = c;
+            sq->cA[i] = -c * si;
+        }
+    }
+    if (threadIdx.x == 0) {
+        int g;
+        if (op == OP_SPE_PUSH1) {
+            const double xx = val[k];
+            g = (sq->push_on && xx > 0.0 && xx <= 1e300) ? 1 : 0;
+            if (b0) {
+                sq->xnorm = sqrt(xx);
+                sq->active = g;
+                sq->a1 = 1.0;
+                sq->slot_new = k;
+                sq->ncol_md = k;
+                sq->accept = 0;     // set by the acceptance test for an accepted column
+                sq->rotate = 0;     // set by OP_SPE_PUSH4 when the window slides
+            }
+        } else {
+            g = sq->active;
+            if (b0) sq->a1 = 1.0;
+        }
+        *gate = g;
+        *kout = k;
+    }
+    __syncthreads();
+}
+
 template <bool DOTS>
 __device__ __forceinline__ void lincomb_body(const LcArgs &a)
 {
-    if (a.active && !*a.active) return;
     __shared__ double sA[kMaxWin], sB[kMaxWin];
     __shared__ double lds[kMaxWin + 3][kMdWaves];
-    const int k = a.kp ? *a.kp : 0;
-    if (threadIdx.x < kMaxWin) {
-        sA[threadIdx.x] = (a.cA && (int)threadIdx.x < k) ? a.cA[threadIdx.x] : 0.0;
-        sB[threadIdx.x] = (a.cB && (int)threadIdx.x < k) ? a.cB[threadIdx.x] : 0.0;
+    __shared__ int s_gate, s_k;
+    int k;
+    double a1;
+    if (a.pre_seq) {
+        if (threadIdx.x < kMaxWin) sB[threadIdx.x] = 0.0;
+        push_coef(a.pre_seq, a.pre_op, a.pin, sA, &s_gate, &s_k);
+        if (!s_gate) return;
+        k = s_k;
+        a1 = 1.0;
+    } else {
+        if (a.active && !*a.active) return;
+        k = a.kp ? *a.kp : 0;
+        if (threadIdx.x < kMaxWin) {
+            sA[threadIdx.x] = (a.cA && (int)threadIdx.x < k) ? a.cA[threadIdx.x] : 0.0;
+            sB[threadIdx.x] = (a.cB && (int)threadIdx.x < k) ? a.cB[threadIdx.x] : 0.0;
+        }
+        __syncthreads();
+        a1 = a.a1 ? *a.a1 : 0.0;
     }
-    __syncthreads();
     double *y1 = a.y1;
     if (a.slot) y1 = const_cast<double *>(a.A) + (int64_t)(*a.slot) * a.ld;
-    const double a1 = a.a1 ? *a.a1 : 0.0, a2 = a.a2 ? *a.a2 : 0.0;
+    const double a2 = a.a2 ? *a.a2 : 0.0;
     const double s2 = a.v2.scale ? *a.v2.scale : 1.0;
     double dots[KC];
 #pragma unroll
@@ -891,15 +884,12 @@ __device__ __forceinline__ void small_body(const SmallArgs &sa)
     switch (op) {
     case OP_SPE_START: nv = sq->k; break;                 // q^T b
     case OP_POD_START: nv = sq->count; break;             // X^T b
-    case OP_SPE_PUSH1: nv = sq->k + 1; break;             // [q, x]^T x
-    case OP_SPE_PUSH2: nv = sq->ncol_md + 3; break;       // q^T w and three norms
-    case OP_SPE_PUSH3: nv = 3; break;                     // norms only
     case OP_SPE_PUSH4: nv = sq->ncol_md; break;           // q^T (K_n + eta D^T D) t
     case OP_POD_PUSH: nv = 2 * sq->npush; break;          // X^T [x, K x]
     default: break;
     }
     nv = nv < 0 ? 0 : (nv > nvals ? nvals : nv);
-    if (part) reduce_rows(part, nv, val);
+    if (part) reduce_rows<kMdStride>(part, nv, val);
     __syncthreads();
     small_op(sq, op, val, sa.tol, sa.info);
 }

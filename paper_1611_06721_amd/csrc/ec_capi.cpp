@@ -644,7 +644,7 @@ struct PushArgs {
     LcArgs l1, l2;
     SlotArgs sa;
     RotArgs ro;
-    SmallArgs s1, s2, s3, s4;
+    SmallArgs s1, s4;       // s1: POD only
 };
 
 static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *x, int set)
@@ -674,25 +674,33 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
     a.m.B[0] = {x, nullptr};
     a.m.nb = 1;
     a.m.active = &sd->push_on;     // only a solution that is due
-    a.s1 = small_args(h, seq, OP_SPE_PUSH1, part);
-    a.l1 = lc_args(h, seq, part);
+    // the dense steps between the products run in the next kernel's blocks:
+    // w = x - q c1 with c1 from q^T x (and the dots q^T w into the upper
+    // half of the partials, which the product's values still occupy below),
+    // x2 = w - q c2, then the acceptance test in the slot SpMV
+    double *part_hi = part + (int64_t)kMaxWin * kMdBlocks;
+    a.l1 = lc_args(h, seq, part_hi);
     a.l1.v1 = x;
     a.l1.y1 = w;
-    a.l1.active = &sd->active;
     a.l1.want_dots = 1;
-    a.s2 = small_args(h, seq, OP_SPE_PUSH2, part);
+    a.l1.pre_seq = sd;
+    a.l1.pre_op = OP_SPE_PUSH1;
+    a.l1.pin = part;
     a.l2 = a.l1;
     a.l2.v1 = w;
     a.l2.y1 = t2;
     a.l2.want_dots = 0;
-    a.s3 = small_args(h, seq, OP_SPE_PUSH3, part);
-    a.sa = SlotArgs{t2, nullptr, KQ, Q, t4, &sd->slot_new, &sd->active, h->seq_eta[seq]};
+    a.l2.pre_op = OP_SPE_PUSH2;
+    a.l2.pin = part_hi;
+    a.l2.part = part;
+    a.sa = SlotArgs{t2, nullptr, KQ, Q, t4, &sd->slot_new, nullptr, h->seq_eta[seq],
+                    sd, part, h->dep_tol};
     a.m2 = md_args(h, part);
     a.m2.A = Q;
     a.m2.kp = &sd->ncol_md;
     a.m2.B[0] = {t4, nullptr};
     a.m2.nb = 1;
-    a.m2.active = &sd->active;
+    a.m2.active = &sd->accept;
     a.s4 = small_args(h, seq, OP_SPE_PUSH4, part);
     a.ro = RotArgs{Q, KQ, sd, h->ld, h->npad};
     return a;
@@ -716,11 +724,8 @@ static void seq_push_n(ec_problem *h, int n, const int *seqs, int method,
         return;
     }
     multidot(a[0].m, st, b ? &b->m : nullptr);
-    small(a[0].s1, st, b ? &b->s1 : nullptr);
     lincomb(a[0].l1, st, b ? &b->l1 : nullptr);
-    small(a[0].s2, st, b ? &b->s2 : nullptr);
     lincomb(a[0].l2, st, b ? &b->l2 : nullptr);
-    small(a[0].s3, st, b ? &b->s3 : nullptr);
     spmv_slots(h->g, h->ld, a[0].sa, st, b ? &b->sa : nullptr);
     multidot(a[0].m2, st, b ? &b->m2 : nullptr);
     small(a[0].s4, st, b ? &b->s4 : nullptr);
@@ -1770,7 +1775,7 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
 // kernel from device tables of per-instance arguments (one block row each).
 struct BasisTab {
     MdArgs *m_start, *m, *m2;
-    SmallArgs *s_start, *s1, *s2, *s3, *s4;
+    SmallArgs *s_start, *s1, *s4;
     LcArgs *l_start, *l1, *l2;
     SlotTab *sa;
     RotArgs *ro;
@@ -1820,8 +1825,6 @@ static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_
         t.m2 = (MdArgs *)take(n * sizeof(MdArgs));
         t.s_start = (SmallArgs *)take(n * sizeof(SmallArgs));
         t.s1 = (SmallArgs *)take(n * sizeof(SmallArgs));
-        t.s2 = (SmallArgs *)take(n * sizeof(SmallArgs));
-        t.s3 = (SmallArgs *)take(n * sizeof(SmallArgs));
         t.s4 = (SmallArgs *)take(n * sizeof(SmallArgs));
         t.l_start = (LcArgs *)take(n * sizeof(LcArgs));
         t.l1 = (LcArgs *)take(n * sizeof(LcArgs));
@@ -1930,7 +1933,7 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
         const int seq = s == 0 ? EC_SEQ_SRC : EC_SEQ_CPL;
         b->tab[s].clear();
         std::vector<MdArgs> ms, m1, m2;
-        std::vector<SmallArgs> ss, s1, s2, s3, s4;
+        std::vector<SmallArgs> ss, s1, s4;
         std::vector<LcArgs> ls, l1, l2;
         std::vector<SlotTab> sa;
         std::vector<RotArgs> ro;
@@ -1950,8 +1953,6 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
             m1.push_back(pa.m);
             m2.push_back(pa.m2);
             s1.push_back(pa.s1);
-            s2.push_back(pa.s2);
-            s3.push_back(pa.s3);
             s4.push_back(pa.s4);
             l1.push_back(pa.l1);
             l2.push_back(pa.l2);
@@ -1975,8 +1976,6 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
         if (!rc) rc = up(t.m2, m2.data(), n * sizeof(MdArgs));
         if (!rc) rc = up(t.s_start, ss.data(), n * sizeof(SmallArgs));
         if (!rc) rc = up(t.s1, s1.data(), n * sizeof(SmallArgs));
-        if (!rc) rc = up(t.s2, s2.data(), n * sizeof(SmallArgs));
-        if (!rc) rc = up(t.s3, s3.data(), n * sizeof(SmallArgs));
         if (!rc) rc = up(t.s4, s4.data(), n * sizeof(SmallArgs));
         if (!rc) rc = up(t.l_start, ls.data(), n * sizeof(LcArgs));
         if (!rc) rc = up(t.l1, l1.data(), n * sizeof(LcArgs));
@@ -2050,11 +2049,8 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
         small_tab(t.s1, n, b->st);
     } else if (meth == EC_SV_SPE) {
         multidot_tab(t.m, n, b->st);
-        small_tab(t.s1, n, b->st);
         lincomb_tab(t.l1, n, true, b->st);
-        small_tab(t.s2, n, b->st);
         lincomb_tab(t.l2, n, false, b->st);
-        small_tab(t.s3, n, b->st);
         spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
         multidot_tab(t.m2, n, b->st);
         small_tab(t.s4, n, b->st);

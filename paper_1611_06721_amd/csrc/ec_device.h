@@ -43,6 +43,34 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Deterministic reduction of nvals <= NV values over the kMdBlocks block
+// partials of a basis product (stored value-major: part[q * kMdBlocks + b])
+// into the shared val[]: the first kMdBlocks threads (four waves) load one
+// row each, every value is a fixed-order wave butterfly and then a fixed-
+// order sum of the four waves.  All threads of the block (at least
+// kMdBlocks) call it; the result does not depend on NV.
+template <int NV>
+__device__ __forceinline__ void reduce_rows(const double *part, int nvals, double *val)
+{
+    __shared__ double tmp[NV][4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < kMdBlocks) {
+        double r[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) r[q] = q < nvals ? part[(int64_t)q * kMdBlocks + tid] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            if (q < nvals) {
+                const double s = wave_sum(r[q]);
+                if (lane == 0) tmp[q][wv] = s;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < nvals) val[tid] = ((tmp[tid][0] + tmp[tid][1]) + tmp[tid][2]) + tmp[tid][3];
+    __syncthreads();
+}
+
 // Sum NV values over a block of blockDim.x <= 1024 threads; every thread
 // gets the sums.  Fixed order: deterministic.
 template <int NV>

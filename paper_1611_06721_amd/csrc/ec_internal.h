@@ -111,6 +111,13 @@ struct SlotArgs {
     double *y, *ycopy, *xcopy, *ypen;
     const int *slot, *active;
     double eta;
+    // if pre_seq: every block first runs the acceptance test of an SPE push
+    // (OP_SPE_PUSH3, |x|^2 from the partials pin, dependency tolerance tol)
+    // and leaves unless the column is accepted (active unused); block 0
+    // stores the test's results
+    SeqDev *pre_seq;
+    const double *pin;
+    double tol;
 };
 void spmv_slots(const Geo &g, int64_t ld, const SlotArgs &s, hipStream_t st,
                 const SlotArgs *s1 = nullptr);
@@ -243,6 +250,13 @@ struct LcArgs {
     int want_dots;           // partial dots A_i^T y1 (i < k) and |y1|^2
     double *part;
     int64_t n;
+    // if pre_seq: every block first runs the dense step pre_op (OP_SPE_PUSH1
+    // or OP_SPE_PUSH2) of that SPE sequence on the partials pin of the
+    // preceding product and takes k, the coefficients, a1 and the gate from
+    // it (kp, cA, a1, active unused); block 0 stores the step's results
+    SeqDev *pre_seq;
+    int pre_op;
+    const double *pin;
 };
 void lincomb(const LcArgs &a, hipStream_t st, const LcArgs *a1 = nullptr);
 void lincomb_tab(const LcArgs *tab, int n, bool dots, hipStream_t st);
@@ -257,13 +271,15 @@ void rotate(const RotArgs &r, hipStream_t st, const RotArgs *r1 = nullptr);
 void rotate_tab(const RotArgs *tab, int n, hipStream_t st);
 
 // dense steps on one sequence: one block reduces the partial rows of the
-// preceding basis product and runs the step
+// preceding basis product and runs the step (PUSH1 and PUSH2 run in every
+// block of the combination that applies them, see LcArgs::pre_op; the
+// acceptance test between them and PUSH4 runs in the slot SpMV)
 enum {
     OP_NONE = -1,
     OP_SPE_START = 0,   // vals: Q_i^T b (k)
     OP_SPE_PUSH1,       // vals: Q_i^T x (k), x^T x
     OP_SPE_PUSH2,       // vals: Q_i^T w (k), |w|^2
-    OP_SPE_PUSH3,       // vals: |x2|^2
+    OP_SPE_PUSH3,       // (unused code: the acceptance test, vals |x2|^2)
     OP_SPE_PUSH4,       // vals: (KQ_i)^T x2, i <= k
     OP_POD_PUSH,        // vals: X_i^T x_new, X_i^T K x_new  (pairs)
     OP_POD_START,       // vals: X_i^T b (count)

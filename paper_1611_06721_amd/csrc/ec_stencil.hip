@@ -51,6 +51,9 @@ struct SpmvArgs {
     T *y, *ycopy, *xcopy, *ypen;
     const int *slot, *active;
     double eta;
+    SeqDev *pre_seq;         // see SlotArgs
+    const double *pin;
+    double tol;
 };
 
 // Blocks are mapped XCD-contiguously (block b runs on XCD b % 8): each XCD
@@ -60,6 +63,30 @@ __device__ __forceinline__ void spmv_box(const Geo &g, int lo0, int lo1, int lo2
                                          int ez, int tiles, int tpx, int64_t ld,
                                          const SpmvArgs<T> &a)
 {
+    if constexpr (std::is_same<T, double>::value) {
+        if (a.pre_seq) {
+            // acceptance test of the pushed column (the dense step of an SPE
+            // push): x2 is not numerically in span(q)
+            __shared__ double s_v[1];
+            __shared__ int s_acc;
+            reduce_rows<1>(a.pin, 1, s_v);
+            if (threadIdx.x == 0) {
+                SeqDev *sq = a.pre_seq;
+                const int k = sq->k;
+                const double rho = sqrt(s_v[0]);
+                const int acc = (sq->active && rho > a.tol * sq->xnorm && k + 1 < kMaxWin) ? 1 : 0;
+                if (blockIdx.x == 0) {
+                    sq->rho = rho;
+                    sq->accept = acc;
+                    if (acc) sq->s[k] = 1.0 / rho;
+                    sq->ncol_md = k + 1;
+                }
+                s_acc = acc;
+            }
+            __syncthreads();
+            if (!s_acc) return;
+        }
+    }
     if (a.active && !*a.active) return;
     const int b = blockIdx.x, tile = (b & 7) * tpx + (b >> 3);
     if (tile >= tiles) return;
@@ -135,6 +162,7 @@ __global__ void __launch_bounds__(256) k_spmv_slot_tab(const SlotTab *tab)
     SpmvArgs<double> a{};
     a.x = e.s.x; a.y = e.s.y; a.ycopy = e.s.ycopy; a.xcopy = e.s.xcopy; a.ypen = e.s.ypen;
     a.slot = e.s.slot; a.active = e.s.active; a.eta = e.s.eta;
+    a.pre_seq = e.s.pre_seq; a.pin = e.s.pin; a.tol = e.s.tol;
     spmv_box<double>(g, 0, 0, 0, ex, ey, ez, tiles, tpx, e.ld, a);
 }
 
@@ -206,6 +234,7 @@ static SpmvArgs<double> slot_args(const SlotArgs &s)
     SpmvArgs<double> a{};
     a.x = s.x; a.y = s.y; a.ycopy = s.ycopy; a.xcopy = s.xcopy; a.ypen = s.ypen;
     a.slot = s.slot; a.active = s.active; a.eta = s.eta;
+    a.pre_seq = s.pre_seq; a.pin = s.pin; a.tol = s.tol;
     return a;
 }
 
