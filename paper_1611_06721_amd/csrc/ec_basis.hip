@@ -45,6 +45,46 @@ __device__ __forceinline__ double lane_read(double v, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// The factorisation half of chol_wave below, statement for statement, for
+// a factor that is stored and used later (same operations, same factor).
+// Cholesky factorisation of H (n x n, leading dimension K, n <= NM) by wave
+// 0, lane r holding row r of the factor in a[] (no block barrier inside):
+// right-looking, column j scaled by the pivot's square root, then the
+// trailing lower triangle updated.  bad: a pivot not positive relative to
+// the largest diagonal entry.
+template <int NM>
+__device__ __forceinline__ void chol_factor_regs(const double *H, int n, double (&a)[NM], int &bad)
+{
+    const int r = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < NM; ++c) a[c] = (r < n && c <= r) ? H[r * K + c] : 0.0;
+    double dg = 0.0;
+#pragma unroll
+    for (int c = 0; c < NM; ++c)
+        if (c == r) dg = a[c];
+    double dmax = r < n ? fabs(dg) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    bad = 0;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+        if (j < n) {
+            const double d = lane_read(a[j], j);
+            if (!(d > 1e-14 * dmax)) bad = 1;
+            const double ljj = d > 0.0 ? sqrt(d) : 1.0;
+            if (r == j) a[j] = ljj;
+            else if (r > j) a[j] /= ljj;
+#pragma unroll
+            for (int c = j + 1; c < NM; ++c) {
+                if (c < n) {
+                    const double lcj = lane_read(a[j], c);
+                    if (r >= c) a[c] -= a[j] * lcj;
+                }
+            }
+        }
+    }
+}
+
 // Cholesky solve H y = g (n x n, leading dimension K, n <= NM) by wave 0,
 // lane r holding row r of the factor in registers (no block barrier inside):
 // right-looking, column j scaled by the pivot's square root, then the
@@ -177,6 +217,63 @@ __device__ bool chol_solve(const double *H, double *L, double *y, const double *
     return s_bad == 0;
 }
 
+// The SPE start's solve H y = g from the factor that the last push stored
+// (SeqDev::L), copied to shared memory Lsh (leading dimension K) and
+// substituted on thread 0 in the operation order of chol_wave's
+// substitutions; false if that factor is not current (then chol_solve).
+__device__ __forceinline__ bool chol_solve_stored(const SeqDev *sq, double *Lsh, double *y,
+                                                  const double *gv, int n, bool *good)
+{
+    __shared__ int s_use, s_bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) {
+        s_use = n <= kCholReg && sq->L_ver == sq->H_ver;
+        s_bad = sq->chol_bad;
+    }
+    __syncthreads();
+    if (!s_use) return false;
+    for (int t = tid; t < n * n; t += nt) {
+        const int r = t / n, c = t - r * n;
+        Lsh[r * K + c] = c <= r ? sq->L[r * K + c] : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 0; i < n; ++i) {
+            double t = gv[i];
+            for (int j = 0; j < i; ++j) t -= Lsh[i * K + j] * y[j];
+            y[i] = t / Lsh[i * K + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int j = i + 1; j < n; ++j) t -= Lsh[j * K + i] * y[j];
+            y[i] = t / Lsh[i * K + i];
+        }
+    }
+    __syncthreads();
+    *good = s_bad == 0;
+    return true;
+}
+
+// Factor H of an SPE sequence into SeqDev::L when a push changed it (wave 0
+// of one block; windows of up to kCholReg columns).
+__device__ __forceinline__ void chol_store(SeqDev *sq)
+{
+    if (threadIdx.x >= 64) return;
+    const int n = sq->k, hv = sq->H_ver;
+    if (sq->L_ver == hv || n < 1 || n > kCholReg) return;
+    double a[kCholReg];
+    int bad;
+    chol_factor_regs<kCholReg>(sq->H, n, a, bad);
+    const int r = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < kCholReg; ++c)
+        if (r < n && c <= r) sq->L[r * K + c] = a[c];
+    if (r == 0) {
+        sq->chol_bad = bad;
+        sq->L_ver = hv;
+    }
+}
+
 // Symmetric eigen-decomposition of A (n x n) by cyclic Jacobi with
 // round-robin pairing (n/2 independent rotations per round), starting from
 // the orthogonal V given; A ends diagonal, the columns of V are eigenvectors.
@@ -249,7 +346,8 @@ __device__ void jacobi_eig(double *A, double *V, int n)
 
 // ------------------------------------------------------- dense steps
 // val: the reduced values of the preceding basis product (see OP_* codes).
-__device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_solve_info *info)
+__device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, double tol,
+                                         ec_solve_info *info)
 {
     __shared__ double Ms[K * K], Ls[K * K], Vs[K * K];
     __shared__ double ys[K + 1], gs[K + 1], sg[K + 1];
@@ -263,7 +361,8 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
         for (int i = tid; i < k; i += nt) gs[i] = sq->s[i] * val[i];
         __syncthreads();
         bool good = k > 0;
-        if (good) good = chol_solve(sq->H, Ls, ys, gs, k);
+        if (good && !chol_solve_stored(sq, Ls, ys, gs, k, &good))
+            good = chol_solve(sq->H, Ls, ys, gs, k);
         // entries are independent: one per thread (no chain of dependent
         // global loads and stores on thread 0)
         for (int i = tid; i < K; i += nt) {
@@ -304,6 +403,7 @@ __device__ void small_op(SeqDev *sq, int op, const double *val, double tol, ec_s
                 sq->R[k * K + k] = sq->rho;
                 sq->k = k + 1;
                 sq->w = sq->w + 1;
+                sq->H_ver = sq->H_ver + 1;   // H grows (and may be downdated below)
             }
         }
         __syncthreads();
@@ -642,7 +742,7 @@ __device__ __forceinline__ void push_coef(SeqDev *sq, int op, const double *pin,
     const int k = sq->k;
     int nv = op == OP_SPE_PUSH1 ? k + 1 : sq->ncol_md + 3;
     nv = nv < 0 ? 0 : (nv > kMaxWin ? kMaxWin : nv);
-    reduce_rows<kMaxWin>(pin, nv, val);
+    reduce_rows<kMaxWin>(pin, kMaxWin, nv, val);
     const bool b0 = blockIdx.x == 0;
     if (threadIdx.x < K) {
         const int i = threadIdx.x;
@@ -813,16 +913,22 @@ __device__ __forceinline__ void rotate_body(const RotArgs &r)
     double *A = r.A, *B = r.B;
     const int64_t ld = r.ld, n = r.n;
     SeqDev *seq = r.seq;
-    const int rot = seq->rotate;
-    // the last kernel of an SPE push: the pushed solution is no longer due
-    if (blockIdx.x == 0 && threadIdx.x == 0) seq->push_on = 0;
-    if (!rot) return;
+    // the last kernel of an SPE push.  Block 0: the pushed solution is no
+    // longer due, and the new H is factored for the next start (beside the
+    // rotation, which the other blocks do)
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) seq->push_on = 0;
+        chol_store(seq);
+        return;
+    }
+    if (!seq->rotate) return;
     __shared__ double R[K * K];
     const int kin = seq->rot_in, kout = seq->rot_k;
     for (int t = threadIdx.x; t < K * K; t += blockDim.x) R[t] = seq->rot[t];
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n; row += stride) {
+    const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
+    for (int64_t row = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x; row < n;
+         row += stride) {
         double va[KC], vb[KC];
 #pragma unroll
         for (int i = 0; i < KC; ++i) {
@@ -873,12 +979,20 @@ void rotate_tab(const RotArgs *tab, int n, hipStream_t st)
 
 // One block per argument set (blockIdx.y): reduce the partial rows of the
 // preceding basis product, then run the dense step `op` of the sequence.
+// OP >= 0: the step is fixed at compile time (one kernel per step, each with
+// the registers of its own step only: a kernel holding every step took all
+// 256 registers and no longer fitted on a CU beside the push kernels of the
+// other branch); OP < 0: sa.op.
+template <int OP>
 __device__ __forceinline__ void small_body(const SmallArgs &sa)
 {
+    // SPE steps read at most cap + 1 <= kMaxWin values
+    constexpr int NV = (OP == OP_SPE_START || OP == OP_SPE_PUSH4) ? kMaxWin : kMdStride;
     SeqDev *sq = sa.seq;
-    const int op = sa.op, nvals = sa.nvals;
+    const int op = OP >= 0 ? OP : sa.op;
+    const int nvals = sa.nvals < NV ? sa.nvals : NV;
     const double *part = sa.part;
-    __shared__ double val[kMdStride];
+    __shared__ double val[NV];
     // exactly the values the producing product kernel wrote (state before the op)
     int nv = nvals;
     switch (op) {
@@ -889,29 +1003,57 @@ __device__ __forceinline__ void small_body(const SmallArgs &sa)
     default: break;
     }
     nv = nv < 0 ? 0 : (nv > nvals ? nvals : nv);
-    if (part) reduce_rows<kMdStride>(part, nv, val);
+    if (part) reduce_rows<NV>(part, nvals, nv, val);
     __syncthreads();
     small_op(sq, op, val, sa.tol, sa.info);
 }
 
+template <int OP>
 __global__ void __launch_bounds__(256) k_small(SmallArgs s0, SmallArgs s1)
 {
-    small_body(blockIdx.y ? s1 : s0);
+    small_body<OP>(blockIdx.y ? s1 : s0);
 }
 
+template <int OP>
 __global__ void __launch_bounds__(256) k_small_tab(const SmallArgs *tab)
 {
-    small_body(tab[blockIdx.y]);
+    small_body<OP>(tab[blockIdx.y]);
 }
 
+template <int OP>
+static void small_launch(const SmallArgs &a, hipStream_t st, const SmallArgs *a1)
+{
+    hipLaunchKernelGGL(k_small<OP>, dim3(1, a1 ? 2 : 1), dim3(256), 0, st, a, a1 ? *a1 : a);
+}
+
+template <int OP>
+static void small_tab_launch(const SmallArgs *tab, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_small_tab<OP>, dim3(1, n), dim3(256), 0, st, tab);
+}
+
+// both sets have the same op
 void small(const SmallArgs &a, hipStream_t st, const SmallArgs *a1)
 {
-    hipLaunchKernelGGL(k_small, dim3(1, a1 ? 2 : 1), dim3(256), 0, st, a, a1 ? *a1 : a);
+    switch (a.op) {
+    case OP_SPE_START: small_launch<OP_SPE_START>(a, st, a1); break;
+    case OP_SPE_PUSH4: small_launch<OP_SPE_PUSH4>(a, st, a1); break;
+    case OP_POD_PUSH: small_launch<OP_POD_PUSH>(a, st, a1); break;
+    case OP_POD_START: small_launch<OP_POD_START>(a, st, a1); break;
+    default: small_launch<-1>(a, st, a1); break;
+    }
 }
 
-void small_tab(const SmallArgs *tab, int n, hipStream_t st)
+// every row of the table has the step op
+void small_tab(const SmallArgs *tab, int n, int op, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_small_tab, dim3(1, n), dim3(256), 0, st, tab);
+    switch (op) {
+    case OP_SPE_START: small_tab_launch<OP_SPE_START>(tab, n, st); break;
+    case OP_SPE_PUSH4: small_tab_launch<OP_SPE_PUSH4>(tab, n, st); break;
+    case OP_POD_PUSH: small_tab_launch<OP_POD_PUSH>(tab, n, st); break;
+    case OP_POD_START: small_tab_launch<OP_POD_START>(tab, n, st); break;
+    default: small_tab_launch<-1>(tab, n, st); break;
+    }
 }
 
 // -------------------------------------------------------- sequence state
@@ -926,6 +1068,7 @@ __global__ void k_seq_reset(SeqDev *sq)
         sq->accept = 0; sq->rotate = 0; sq->active = 0; sq->flags = 0; sq->zero_start = 1;
         sq->ncol_md = 0; sq->npush = 1; sq->slot_new = 0; sq->pod_info = 1.0; sq->rot_in = 0;
         sq->rot_k = 0; sq->push_on = 0;
+        sq->H_ver = 0; sq->L_ver = 0; sq->chol_bad = 0;
         for (int i = 0; i <= K; ++i) sq->s[i] = 1.0;
     }
 }

@@ -586,7 +586,9 @@ static SmallArgs small_args(ec_problem *h, int seq, int op, const double *part,
     a.seq = h->seq_d + seq;
     a.op = op;
     a.part = part;
-    a.nvals = kMdStride;
+    // values a dense step can read: SPE k <= cap, ncol_md <= cap + 1; POD
+    // 2 npush <= 2 cap, count <= cap (loaded before the count is known)
+    a.nvals = std::min(kMdStride, 2 * h->cap + 2);
     a.tol = h->dep_tol;
     a.info = info;
     return a;
@@ -2007,7 +2009,7 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
     }
     if (basis) {                 // start vectors of all instances (eqs. 10, 14)
         multidot_tab(t.m_start, n, b->st);
-        small_tab(t.s_start, n, b->st);
+        small_tab(t.s_start, n, meth == EC_SV_POD ? OP_POD_START : OP_SPE_START, b->st);
         lincomb_tab(t.l_start, n, false, b->st);
     }
     // PCG inits of all instances (same start method, so the same mode)
@@ -2046,14 +2048,14 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
     if (meth == EC_SV_POD) {     // histories of all instances
         spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
         multidot_tab(t.m, n, b->st);
-        small_tab(t.s1, n, b->st);
+        small_tab(t.s1, n, OP_POD_PUSH, b->st);
     } else if (meth == EC_SV_SPE) {
         multidot_tab(t.m, n, b->st);
         lincomb_tab(t.l1, n, true, b->st);
         lincomb_tab(t.l2, n, false, b->st);
         spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
         multidot_tab(t.m2, n, b->st);
-        small_tab(t.s4, n, b->st);
+        small_tab(t.s4, n, OP_SPE_PUSH4, b->st);
         rotate_tab(t.ro, n, b->st);
     }
     return launch_check(h0, "batch solve");

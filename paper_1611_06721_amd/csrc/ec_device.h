@@ -48,16 +48,19 @@ __device__ __forceinline__ double wave_sum(double v)
 // into the shared val[]: the first kMdBlocks threads (four waves) load one
 // row each, every value is a fixed-order wave butterfly and then a fixed-
 // order sum of the four waves.  All threads of the block (at least
-// kMdBlocks) call it; the result does not depend on NV.
+// kMdBlocks) call it; the result does not depend on NV or nload.  The loads
+// cover the first nload >= nvals values (a bound known before the count:
+// they need not wait for the load that gives nvals; the partials buffer
+// holds kMdStride values per block).
 template <int NV>
-__device__ __forceinline__ void reduce_rows(const double *part, int nvals, double *val)
+__device__ __forceinline__ void reduce_rows(const double *part, int nload, int nvals, double *val)
 {
     __shared__ double tmp[NV][4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < kMdBlocks) {
         double r[NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) r[q] = q < nvals ? part[(int64_t)q * kMdBlocks + tid] : 0.0;
+        for (int q = 0; q < NV; ++q) r[q] = q < nload ? part[(int64_t)q * kMdBlocks + tid] : 0.0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             if (q < nvals) {

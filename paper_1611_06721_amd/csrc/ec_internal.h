@@ -75,6 +75,11 @@ struct SeqDev {
     // start vector, which lies in span(q), so the dependency test of the
     // push would reject it); the push kernels are gated on it
     int push_on;
+    // SPE: Cholesky factor of H (lower, leading dimension kMaxWin) made by
+    // the last kernel of a push; valid while L_ver == H_ver (H_ver counts
+    // the pushes that changed H); chol_bad: H not numerically definite
+    int H_ver, L_ver, chol_bad, pad3;
+    double L[kMaxWin * kMaxWin];
 };
 
 // Per-handle control block in device memory.
@@ -294,7 +299,7 @@ struct SmallArgs {
     ec_solve_info *info;
 };
 void small(const SmallArgs &a, hipStream_t st, const SmallArgs *a1 = nullptr);
-void small_tab(const SmallArgs *tab, int n, hipStream_t st);
+void small_tab(const SmallArgs *tab, int n, int op, hipStream_t st);
 void seq_reset(SeqDev *seq, hipStream_t st);
 
 // nonlinear a_c update (eq. 6) / K_c + K_cn apply over conducting edges

@@ -69,7 +69,7 @@ __device__ __forceinline__ void spmv_box(const Geo &g, int lo0, int lo1, int lo2
             // push): x2 is not numerically in span(q)
             __shared__ double s_v[1];
             __shared__ int s_acc;
-            reduce_rows<1>(a.pin, 1, s_v);
+            reduce_rows<1>(a.pin, 1, 1, s_v);
             if (threadIdx.x == 0) {
                 SeqDev *sq = a.pre_seq;
                 const int k = sq->k;
