@@ -381,6 +381,55 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
         }
         break;
     }
+    // PUSH1-3: the one-block form of the steps that push_coef and the slot
+    // SpMV's acceptance test run in every block (batched pushes, where each
+    // instance's grid is mostly small): the same expressions on the same
+    // reduced values
+    case OP_SPE_PUSH1: {
+        // c1 = q^T x; w = x - q c1
+        for (int i = tid; i < K; i += nt) {
+            const double si = i < k ? sq->s[i] : 0.0;
+            const double c1 = si * (i < k ? val[i] : 0.0);
+            sq->c1[i] = c1;
+            sq->cA[i] = -c1 * si;
+        }
+        if (tid == 0) {
+            const double xx = val[k];
+            sq->xnorm = sqrt(xx);
+            sq->active = (sq->push_on && xx > 0.0 && xx <= 1e300) ? 1 : 0;
+            sq->a1 = 1.0;
+            sq->slot_new = k;
+            sq->ncol_md = k;
+            sq->accept = 0;     // set by the acceptance test for an accepted column
+            sq->rotate = 0;     // set by OP_SPE_PUSH4 when the window slides
+        }
+        break;
+    }
+    case OP_SPE_PUSH2: {
+        // second pass: c2 = q^T w; x2 = w - q c2
+        for (int i = tid; i < K; i += nt) {
+            const double si = i < k ? sq->s[i] : 0.0;
+            const double c2 = si * (i < k ? val[i] : 0.0);
+            sq->c2[i] = c2;
+            sq->cA[i] = -c2 * si;
+        }
+        if (tid == 0) sq->a1 = 1.0;
+        break;
+    }
+    case OP_SPE_PUSH3: {
+        // accept x2 if it is not (numerically) in span(q): a linearly
+        // independent new column
+        if (tid == 0) {
+            const double rho = sqrt(val[0]);
+            sq->rho = rho;
+            const int acc = (sq->active && rho > tol * sq->xnorm && k + 1 < K) ? 1 : 0;
+            sq->accept = acc;
+            sq->active = acc;
+            if (acc) sq->s[k] = 1.0 / rho;
+            sq->ncol_md = k + 1;
+        }
+        break;
+    }
     case OP_SPE_PUSH4: {
         // new row/column of H = q^T K q and of the window coordinates R
         const int acc = sq->accept;
@@ -778,7 +827,9 @@ __device__ __forceinline__ void push_coef(SeqDev *sq, int op, const double *pin,
     __syncthreads();
 }
 
-template <bool DOTS>
+// PRE: the kernel can run a dense step first (a.pre_seq); the table
+// kernels of batched pushes never do, and leave that code out.
+template <bool DOTS, bool PRE = true>
 __device__ __forceinline__ void lincomb_body(const LcArgs &a)
 {
     __shared__ double sA[kMaxWin], sB[kMaxWin];
@@ -786,7 +837,7 @@ __device__ __forceinline__ void lincomb_body(const LcArgs &a)
     __shared__ int s_gate, s_k;
     int k;
     double a1;
-    if (a.pre_seq) {
+    if (PRE && a.pre_seq) {
         if (threadIdx.x < kMaxWin) sB[threadIdx.x] = 0.0;
         push_coef(a.pre_seq, a.pre_op, a.pin, sA, &s_gate, &s_k);
         if (!s_gate) return;
@@ -881,7 +932,7 @@ __global__ void __launch_bounds__(kMdThreads) k_lincomb(LcPair sets)
 template <bool DOTS>
 __global__ void __launch_bounds__(kMdThreads) k_lincomb_tab(const LcArgs *tab)
 {
-    lincomb_body<DOTS>(tab[blockIdx.y]);
+    lincomb_body<DOTS, false>(tab[blockIdx.y]);
 }
 
 // both sets (and every table row) have the same want_dots
@@ -998,6 +1049,9 @@ __device__ __forceinline__ void small_body(const SmallArgs &sa)
     switch (op) {
     case OP_SPE_START: nv = sq->k; break;                 // q^T b
     case OP_POD_START: nv = sq->count; break;             // X^T b
+    case OP_SPE_PUSH1: nv = sq->k + 1; break;             // [q, x]^T x
+    case OP_SPE_PUSH2: nv = sq->ncol_md + 3; break;       // q^T w and three norms
+    case OP_SPE_PUSH3: nv = 3; break;                     // norms only
     case OP_SPE_PUSH4: nv = sq->ncol_md; break;           // q^T (K_n + eta D^T D) t
     case OP_POD_PUSH: nv = 2 * sq->npush; break;          // X^T [x, K x]
     default: break;

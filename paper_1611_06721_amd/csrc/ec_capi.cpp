@@ -646,10 +646,15 @@ struct PushArgs {
     LcArgs l1, l2;
     SlotArgs sa;
     RotArgs ro;
-    SmallArgs s1, s4;       // s1: POD only
+    SmallArgs s1, s2, s3, s4;   // s1-s3: the one-block form (batched SPE pushes, POD)
 };
 
-static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *x, int set)
+// fused: the SPE coefficient steps and the acceptance test run in the
+// blocks of the kernels that apply them (one problem); otherwise as
+// one-block steps (batched pushes: most of an instance's blocks have little
+// work, and each would repeat the step's reduction)
+static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *x, int set,
+                              bool fused = true)
 {
     double *w = set ? h->w_b : h->w, *t2 = set ? h->t2_b : h->t2;
     double *t3 = set ? h->t3_b : h->t3, *t4 = set ? h->t4_b : h->t4;
@@ -697,6 +702,18 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
     a.l2.part = part;
     a.sa = SlotArgs{t2, nullptr, KQ, Q, t4, &sd->slot_new, nullptr, h->seq_eta[seq],
                     sd, part, h->dep_tol};
+    if (!fused) {
+        a.s1 = small_args(h, seq, OP_SPE_PUSH1, part);
+        a.s2 = small_args(h, seq, OP_SPE_PUSH2, part);
+        a.s3 = small_args(h, seq, OP_SPE_PUSH3, part);
+        for (LcArgs *l : {&a.l1, &a.l2}) {
+            l->pre_seq = nullptr;
+            l->active = &sd->active;
+            l->part = part;
+        }
+        a.sa.pre_seq = nullptr;
+        a.sa.active = &sd->active;
+    }
     a.m2 = md_args(h, part);
     a.m2.A = Q;
     a.m2.kp = &sd->ncol_md;
@@ -1777,7 +1794,7 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
 // kernel from device tables of per-instance arguments (one block row each).
 struct BasisTab {
     MdArgs *m_start, *m, *m2;
-    SmallArgs *s_start, *s1, *s4;
+    SmallArgs *s_start, *s1, *s2, *s3, *s4;
     LcArgs *l_start, *l1, *l2;
     SlotTab *sa;
     RotArgs *ro;
@@ -1826,6 +1843,8 @@ static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_
         t.m = (MdArgs *)take(n * sizeof(MdArgs));
         t.m2 = (MdArgs *)take(n * sizeof(MdArgs));
         t.s_start = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.s2 = (SmallArgs *)take(n * sizeof(SmallArgs));
+        t.s3 = (SmallArgs *)take(n * sizeof(SmallArgs));
         t.s1 = (SmallArgs *)take(n * sizeof(SmallArgs));
         t.s4 = (SmallArgs *)take(n * sizeof(SmallArgs));
         t.l_start = (LcArgs *)take(n * sizeof(LcArgs));
@@ -1935,7 +1954,7 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
         const int seq = s == 0 ? EC_SEQ_SRC : EC_SEQ_CPL;
         b->tab[s].clear();
         std::vector<MdArgs> ms, m1, m2;
-        std::vector<SmallArgs> ss, s1, s4;
+        std::vector<SmallArgs> ss, s1, s2, s3, s4;
         std::vector<LcArgs> ls, l1, l2;
         std::vector<SlotTab> sa;
         std::vector<RotArgs> ro;
@@ -1951,10 +1970,12 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
             ms.push_back(st.m);
             ss.push_back(st.s);
             ls.push_back(st.l);
-            const PushArgs pa = seq_push_args(h, seq, meth, a.x, 0);
+            const PushArgs pa = seq_push_args(h, seq, meth, a.x, 0, false);
             m1.push_back(pa.m);
             m2.push_back(pa.m2);
             s1.push_back(pa.s1);
+            s2.push_back(pa.s2);
+            s3.push_back(pa.s3);
             s4.push_back(pa.s4);
             l1.push_back(pa.l1);
             l2.push_back(pa.l2);
@@ -1978,6 +1999,8 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
         if (!rc) rc = up(t.m2, m2.data(), n * sizeof(MdArgs));
         if (!rc) rc = up(t.s_start, ss.data(), n * sizeof(SmallArgs));
         if (!rc) rc = up(t.s1, s1.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.s2, s2.data(), n * sizeof(SmallArgs));
+        if (!rc) rc = up(t.s3, s3.data(), n * sizeof(SmallArgs));
         if (!rc) rc = up(t.s4, s4.data(), n * sizeof(SmallArgs));
         if (!rc) rc = up(t.l_start, ls.data(), n * sizeof(LcArgs));
         if (!rc) rc = up(t.l1, l1.data(), n * sizeof(LcArgs));
@@ -2051,8 +2074,11 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
         small_tab(t.s1, n, OP_POD_PUSH, b->st);
     } else if (meth == EC_SV_SPE) {
         multidot_tab(t.m, n, b->st);
+        small_tab(t.s1, n, OP_SPE_PUSH1, b->st);
         lincomb_tab(t.l1, n, true, b->st);
+        small_tab(t.s2, n, OP_SPE_PUSH2, b->st);
         lincomb_tab(t.l2, n, false, b->st);
+        small_tab(t.s3, n, OP_SPE_PUSH3, b->st);
         spmv_slots_tab(t.sa, n, b->slot_tpx, b->st);
         multidot_tab(t.m2, n, b->st);
         small_tab(t.s4, n, OP_SPE_PUSH4, b->st);

@@ -276,15 +276,15 @@ void rotate(const RotArgs &r, hipStream_t st, const RotArgs *r1 = nullptr);
 void rotate_tab(const RotArgs *tab, int n, hipStream_t st);
 
 // dense steps on one sequence: one block reduces the partial rows of the
-// preceding basis product and runs the step (PUSH1 and PUSH2 run in every
-// block of the combination that applies them, see LcArgs::pre_op; the
-// acceptance test between them and PUSH4 runs in the slot SpMV)
+// preceding basis product and runs the step (for a single problem, PUSH1
+// and PUSH2 run in every block of the combination that applies them, see
+// LcArgs::pre_op, and PUSH3 in the slot SpMV, see SlotArgs::pre_seq)
 enum {
     OP_NONE = -1,
     OP_SPE_START = 0,   // vals: Q_i^T b (k)
     OP_SPE_PUSH1,       // vals: Q_i^T x (k), x^T x
     OP_SPE_PUSH2,       // vals: Q_i^T w (k), |w|^2
-    OP_SPE_PUSH3,       // (unused code: the acceptance test, vals |x2|^2)
+    OP_SPE_PUSH3,       // vals: |x2|^2 (acceptance test)
     OP_SPE_PUSH4,       // vals: (KQ_i)^T x2, i <= k
     OP_POD_PUSH,        // vals: X_i^T x_new, X_i^T K x_new  (pairs)
     OP_POD_START,       // vals: X_i^T b (count)
