@@ -207,6 +207,24 @@ def test_spe_exact_and_random_window(ec, oracle_mod):
     assert np.linalg.norm(x1 - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+def test_spe_large_window(ec, oracle_mod):
+    """Windows wider than the register Cholesky (12 columns): the start
+    factors H in shared memory; the sliding window (13 of 15 pushes) and the
+    stored-factor start of a 12-column window agree with the oracle."""
+    from oracle.startvec import spe_start
+    G, O, _ = pair(ec, oracle_mod, "small", cap=16)
+    win = [O.kn(synth.random_vector(O.n_pad, O.N, 60 + s)) for s in range(15)]
+    b = O.source(1, 1e-3) + O.kcnT(synth.random_vector(O.n_pad, O.C, 7))
+    for w in (13, 12):
+        seq = ec.SEQ_ADJ
+        G.history_reset(seq)
+        for v in win:
+            G.history_push(seq, ec.SV_SPE, w, G.tensor(v))
+        x0 = G.start_vector(seq, ec.SV_SPE, w, G.tensor(b)).cpu().numpy()
+        ref = spe_start(O, win[-w:], b)
+        assert np.linalg.norm(x0 - ref) <= 1e-9 * np.linalg.norm(ref), w
+
+
 def test_spe_gauge_penalty(ec, oracle_mod):
     """A window holding a pure gradient (a null vector of K_n): with the
     grad-div term the start vector is x* itself, as in the oracle; with the
