@@ -795,8 +795,10 @@ constexpr int kGraphMaxIters = 4096;
 // device done flag of the previous chunk (pinned copy) while the next chunk
 // runs; the first chunk is the previous iteration count of the sequence.
 template <typename T>
-static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hintable, int *n_issued)
+static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hintable, int *n_issued,
+                          bool *fin_done = nullptr)
 {
+    if (fin_done) *fin_done = false;
     hipStream_t st = h->st;
     const int maxit = a.maxit;
     if (capturing(h)) {
@@ -815,9 +817,12 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
         // in one persistent launch instead of failing at the budget
         if constexpr (std::is_same<T, double>::value) {
             if (tail) {
-                hipError_t e = cg_tail<double>(a, kernels, h->tail_blocks, st);
+                // the tail also runs the solve's final step when the caller
+                // takes it (one launch fewer)
+                hipError_t e = cg_tail<double>(a, kernels, h->tail_blocks, st, fin_done != nullptr);
                 if (e != hipSuccess)
                     return fail(h, EC_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
+                if (fin_done) *fin_done = true;
             }
         }
         *n_issued = budget;
@@ -904,9 +909,10 @@ static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const
     CgArgs<double> a = cg64_args(h, seq, b, bscale, x, o, info);
     cg64_init(h, a, mode);
     int issued = 0;
-    int32_t rc = cg_iterate<double>(h, a, seq, true, &issued);
+    bool fin_done = false;
+    int32_t rc = cg_iterate<double>(h, a, seq, true, &issued, &fin_done);
     if (rc) return rc;
-    cg_fin<double>(a, issued, h->st);
+    if (!fin_done) cg_fin<double>(a, issued, h->st);
     return launch_check(h, "cg fin");
 }
 

@@ -220,7 +220,7 @@ template <typename T>
 int cg_tail_blocks();
 // iterations it0.. of an unfinished solve in one persistent launch
 template <typename T>
-hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st);
+hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st, bool fin);
 
 // basis products  C = [A_0..A_{p-1}, a_extra]^T [B_0..B_{nb-1}]  (FP64 MFMA)
 struct MdArgs {

@@ -1029,16 +1029,23 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned gen, BarSta
 // iterations it0, it0+1, ... in one persistent launch, a grid barrier
 // between iterations, until the (uniform) convergence / maxit decision.
 // Ends with the final record in slot (it0 + 1) & 1 (in both slots when it
-// took more than one iteration).
+// took more than one iteration); with fin, block 0 then runs the solve's
+// final step (k_cg_fin for it0 + 1 iteration launches), one launch fewer.
 // HOISTED: every block sweeps at most one tile (the iteration kernels' form,
 // chosen on the host so that each instantiation holds only one path).
+template <typename T>
+__device__ __forceinline__ void cg_fin_body(const CgArgs<T> &a, int iters);
+
 template <typename T, bool HOISTED>
-__global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsigned *bar)
+__global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsigned *bar, int fin)
 {
     if (a.skip && *a.skip) return;
     // the usual case: the captured kernels finished the solve
     if (a.ctl[it0 & 1].done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl[(it0 + 1) & 1] = a.ctl[it0 & 1];
+        if (blockIdx.x == 0) {
+            if (threadIdx.x == 0) a.ctl[(it0 + 1) & 1] = a.ctl[it0 & 1];
+            if (fin) cg_fin_body<T>(a, it0 + 1);
+        }
         return;
     }
     __shared__ CgCtl s_c;
@@ -1060,8 +1067,11 @@ __global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsign
         if (!ok) break;
     }
     // decided in its first iteration: that decision already stored the
-    // record in slot (it0 + 1) & 1, the one the final kernel reads
-    if (ok && it == it0) return;
+    // record in slot (it0 + 1) & 1, the one the final step reads
+    if (ok && it == it0) {
+        if (fin && blockIdx.x == 0) cg_fin_body<T>(a, it0 + 1);
+        return;
+    }
     // every block has read the control slots of its last iteration
     if (ok) ok = grid_barrier(bar, ++gen, bs);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1073,6 +1083,8 @@ __global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsign
         a.ctl[0] = f;
         a.ctl[1] = f;
     }
+    // the solve's final step (as k_cg_fin) on the record just stored
+    if (fin && blockIdx.x == 0) cg_fin_body<T>(a, it0 + 1);
 }
 
 // After `iters` iteration kernels: final decision on the last iterate, the
@@ -1184,16 +1196,18 @@ int cg_tail_blocks()
 }
 
 template <typename T>
-hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st)
+hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st, bool fin)
 {
     // a plain launch: a cooperative one costs ~11 us of idle device on each
     // side inside a graph; co-residency holds because the grid fits the
     // device at once and stream order leaves it empty, and the bounded wait
     // of the barrier turns any violation into an error status
     if ((blocks >> 3) >= ((a.tiles + 7) >> 3))
-        hipLaunchKernelGGL((k_cg_tail<T, true>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar);
+        hipLaunchKernelGGL((k_cg_tail<T, true>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar,
+                           fin ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_cg_tail<T, false>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar);
+        hipLaunchKernelGGL((k_cg_tail<T, false>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar,
+                           fin ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1209,7 +1223,7 @@ template void cg_init<float>(const CgArgs<float> &, hipStream_t);
 template void cg_iter<float>(const CgArgs<float> &, int, hipStream_t);
 template void cg_fin<float>(const CgArgs<float> &, int, hipStream_t);
 template int cg_tail_blocks<double>();
-template hipError_t cg_tail<double>(const CgArgs<double> &, int, int, hipStream_t);
+template hipError_t cg_tail<double>(const CgArgs<double> &, int, int, hipStream_t, bool);
 
 // --------------------------------------------------- FP32-refined solves
 // r = s b - K_n x in FP64, r32 = r, partials (|r|^2, |b|^2).
