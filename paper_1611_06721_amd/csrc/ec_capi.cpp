@@ -594,10 +594,6 @@ static SmallArgs small_args(ec_problem *h, int seq, int op, const double *part,
     return a;
 }
 
-static void dense(ec_problem *h, int seq, int op, ec_solve_info *info = nullptr)
-{
-    small(small_args(h, seq, op, h->part_md, info), h->st);
-}
 
 // Arguments of the three launches of a start vector: x0 and r0 = b - K_n x0
 // (into rb[0]) from the history of seq (eqs. 10, 14)
@@ -663,7 +659,7 @@ static PushArgs seq_push_args(ec_problem *h, int seq, int method, const double *
     double *Q = basis_Q(h, seq), *KQ = basis_KQ(h, seq);
     PushArgs a{};
     if (method == EC_SV_POD) {
-        a.sa = SlotArgs{x, t3, KQ, Q, nullptr, &sd->slot_new, &sd->push_on, 0.0};
+        a.sa = SlotArgs{x, t3, KQ, Q, nullptr, &sd->slot_new, &sd->push_on, 0.0, nullptr, nullptr, 0.0};
         a.m = md_args(h, part);
         a.m.active = &sd->push_on;      // only a solution that is due
         a.m.A = Q;
