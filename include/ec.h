@@ -130,10 +130,13 @@ typedef struct {
      * B - 1 iteration kernels and then one persistent kernel that takes the
      * B-th iteration and any further ones up to solve.maxit (same iterates:
      * with at most one 256-node tile per block the results do not depend on
-     * the budget); an FP32-refined inner pass
-     * stops at the budget and the FP64 outer loop goes on.  A solve short of
-     * its tolerance at solve.maxit ends with EC_ERR_NOT_CONVERGED in its
-     * record and in the worst-status counter.  Eager calls ignore these. */
+     * the budget).  An FP32-refined solve issues every outer pass up to
+     * solve.outer_max (a pass after the FP64 check has passed does
+     * nothing): the first inner PCG as above with B and inner_maxit, each
+     * later one as one iteration kernel and the persistent kernel (passes
+     * after the first are short corrections).  A solve short of its
+     * tolerance at solve.maxit ends with EC_ERR_NOT_CONVERGED in its record
+     * and in the worst-status counter.  Eager calls ignore these. */
     int32_t graph_iters[2];
     /* 1: a captured step runs as one chain of kernels.  0 (default): with an
      * SPE or POD history and FP64 solves, the history pushes run on a forked

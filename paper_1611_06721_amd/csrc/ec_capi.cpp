@@ -83,7 +83,8 @@ struct ec_problem {
     CgCtl *cg_d = nullptr;
     double *part_cg = nullptr, *part_md = nullptr, *part_ref = nullptr, *part_md_b = nullptr;
     unsigned *bar = nullptr;     // grid-barrier counters of the PCG tail kernel
-    int tail_blocks = 0;         // persistent tail grid (0: no tail available)
+    int tail_blocks = 0;         // persistent tail grid, FP64 (0: no tail available)
+    int tail_blocks_f = 0;       // the same for the FP32 inner solves
     // 2.5D PCG iteration (large grids): column width, planes per block, tile
     // counts and its grid; used while cg_blocks == grid25
     int t25 = 0, kb25 = 0, nti25 = 0, ntj25 = 0, ntk25 = 0, grid25 = 0, node_blocks = 0;
@@ -497,6 +498,7 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
     h->node_blocks = choose_blocks(h);
     h->cg_blocks = plan_25(h, false) ? h->grid25 : h->node_blocks;
     h->tail_blocks = cg_tail_blocks<double>();
+    h->tail_blocks_f = cg_tail_blocks<float>();
     h->bound = true;
     return EC_OK;
 }
@@ -790,20 +792,23 @@ constexpr int kGraphMaxIters = 4096;
 // convergence).  Eagerly, iterations go out in chunks and the host reads the
 // device done flag of the previous chunk (pinned copy) while the next chunk
 // runs; the first chunk is the previous iteration count of the sequence.
+// want_cap > 0: a captured solve issues at most that many iteration kernels
+// (with the tail, the last of them is the tail).
 template <typename T>
 static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hintable, int *n_issued,
-                          bool *fin_done = nullptr)
+                          bool *fin_done = nullptr, int want_cap = 0)
 {
     if (fin_done) *fin_done = false;
     hipStream_t st = h->st;
     const int maxit = a.maxit;
     if (capturing(h)) {
         int budget = std::min(maxit, kGraphMaxIters);
-        // the sequence budget caps the FP64 solve (the tail finishes it) or
-        // each inner FP32 pass of a refined solve (the outer loop goes on)
-        const int want = h->graph_iters[seq];
-        const bool tail = hintable && want > 0 && want < maxit &&
-                          std::is_same<T, double>::value && h->tail_blocks > 0;
+        // the sequence budget caps the FP64 solve or each inner FP32 pass of
+        // a refined solve; the tail finishes either
+        int want = h->graph_iters[seq];
+        if (want > 0 && want_cap > 0) want = std::min(want, want_cap);
+        const int tblocks = std::is_same<T, double>::value ? h->tail_blocks : h->tail_blocks_f;
+        const bool tail = want > 0 && want < maxit && tblocks > 0;
         if (want > 0) budget = std::min(budget, want);
         // with the tail, it runs the last budgeted iteration itself (the same
         // iteration body; one launch fewer when the solve is already done)
@@ -811,15 +816,13 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
         for (int i = 0; i < kernels; ++i) cg_iter<T>(a, i, st);
         // rare long solves (cold start, a sudden change of the source) finish
         // in one persistent launch instead of failing at the budget
-        if constexpr (std::is_same<T, double>::value) {
-            if (tail) {
-                // the tail also runs the solve's final step when the caller
-                // takes it (one launch fewer)
-                hipError_t e = cg_tail<double>(a, kernels, h->tail_blocks, st, fin_done != nullptr);
-                if (e != hipSuccess)
-                    return fail(h, EC_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
-                if (fin_done) *fin_done = true;
-            }
+        if (tail) {
+            // the tail also runs the solve's final step when the caller
+            // takes it (one launch fewer)
+            hipError_t e = cg_tail<T>(a, kernels, tblocks, st, fin_done != nullptr);
+            if (e != hipSuccess)
+                return fail(h, EC_ERR_HIP, "tail launch: %s", hipGetErrorString(e));
+            if (fin_done) *fin_done = true;
         }
         *n_issued = budget;
         return launch_check(h, "cg (graph)");
@@ -954,10 +957,14 @@ static int32_t run_refined(ec_problem *h, int seq, const double *b, const double
         a.skip = &h->ctrl_d->refine_done;
         a.tiles = h->tiles;
         a.blocks = h->cg_blocks;
+        a.bar = h->bar;
         set_25(h, a);
         cg_init<float>(a, st);
         int issued = 0;
-        int32_t rc = cg_iterate<float>(h, a, seq, false, &issued);
+        // captured: the first pass gets the sequence budget; a later pass is
+        // a correction the first one rarely leaves (it is skipped once the
+        // FP64 check has passed), so it issues one kernel and the tail
+        int32_t rc = cg_iterate<float>(h, a, seq, false, &issued, nullptr, pass == 0 ? 0 : 2);
         if (rc) return rc;
         cg_fin<float>(a, issued, st);
         refine_update(x, h->fd, h->ctrl_d, h->npad, st);

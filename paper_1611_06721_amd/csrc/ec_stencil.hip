@@ -1224,6 +1224,8 @@ template void cg_iter<float>(const CgArgs<float> &, int, hipStream_t);
 template void cg_fin<float>(const CgArgs<float> &, int, hipStream_t);
 template int cg_tail_blocks<double>();
 template hipError_t cg_tail<double>(const CgArgs<double> &, int, int, hipStream_t, bool);
+template int cg_tail_blocks<float>();
+template hipError_t cg_tail<float>(const CgArgs<float> &, int, int, hipStream_t, bool);
 
 // --------------------------------------------------- FP32-refined solves
 // r = s b - K_n x in FP64, r32 = r, partials (|r|^2, |b|^2).
