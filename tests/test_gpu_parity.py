@@ -527,6 +527,36 @@ def test_refined_graph_replay_equals_eager(ec, oracle_mod):
     assert np.array_equal(A2.cpu().numpy(), A1.cpu().numpy())
 
 
+def test_refined_graph_starved_budget_equals_eager(ec, oracle_mod):
+    """Captured FP32-refined steps whose inner passes get two iteration
+    kernels each: the persistent FP32 tail takes every further iteration of
+    every pass, and the trajectory is still the eager one, bit for bit (one
+    256-node tile per block on this grid, so the tail's sums are the
+    iteration kernel's)."""
+    G1, O, wl = pair(ec, oracle_mod, "c1")
+    dt = 0.9 * 2 / O.power(iters=40)
+    kw = dict(rtol=1e-10, precision=ec.PREC_FP32_REFINED, inner_rtol=1e-5, inner_maxit=60,
+              outer_max=4)
+    opts = ec.step_opts(ec.SV_SPE, window=5, **kw)
+    A1 = G1.zeros()
+    G1.set_state(A1, rtol=1e-10)
+    info1 = G1.info(2 * 25)
+    G1.run(A1, 0, 25, dt, opts, info=info1)
+    its = ec.info_array(info1)["iters"][20:]
+    assert its.max() > 2                    # the tail has work to do
+    G2 = ec.Problem(wl, window_cap=8)
+    A2 = G2.zeros()
+    G2.set_state(A2, rtol=1e-10)
+    G2.run(A2, 0, 10, dt, opts)
+    G2.counters_reset()
+    g = G2.graph_capture(A2, dt, ec.step_opts(ec.SV_SPE, window=5, graph_iters=(2, 2), **kw))
+    for _ in range(15):
+        g.launch()
+    c = G2.counters()
+    assert c["worst_status"] == 0 and c["steps"] == 15
+    assert np.array_equal(A2.cpu().numpy(), A1.cpu().numpy())
+
+
 # ------------------------------------------------ 2.5D (LDS-staged) PCG kernel
 @pytest.mark.parametrize("name", ["c1", "lshape", "nl16"])
 def test_tiled_pcg_kernel_parity(ec, oracle_mod, name):
