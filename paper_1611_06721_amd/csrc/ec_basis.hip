@@ -277,25 +277,31 @@ __device__ __forceinline__ void chol_store(SeqDev *sq)
 // Symmetric eigen-decomposition of A (n x n) by cyclic Jacobi with
 // round-robin pairing (n/2 independent rotations per round), starting from
 // the orthogonal V given; A ends diagonal, the columns of V are eigenvectors.
+// A is a Gram matrix (positive semidefinite) formed in FP64, so its entries
+// carry absolute errors of order eps trace(A): an entry is annihilated only
+// while |a_pq| > 1e-14 sqrt(a_pp a_qq) + 1e-15 trace(A), and the sweeps end
+// with the first one that rotates nothing (a test on the whole off-diagonal
+// mass against 1e-30 of the diagonal's rarely passed once rounding noise
+// dominated it, so most calls ran the sweep limit; a purely relative
+// threshold never passes on such a matrix).
 __device__ void jacobi_eig(double *A, double *V, int n)
 {
     __shared__ double cs[K / 2 + 1][2];
     __shared__ int pr[K / 2 + 1][2];
-    __shared__ int s_done;
+    __shared__ int s_rot;
+    __shared__ double s_tr;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int m = (n + 1) & ~1;
+    if (tid == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < n; ++i) tr += fabs(A[i * K + i]);
+        s_tr = tr;
+    }
+    __syncthreads();
+    const double floor_abs = 1e-15 * s_tr;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) {
-            double off = 0.0, dia = 0.0;
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j) {
-                    const double x = A[i * K + j] * A[i * K + j];
-                    if (i == j) dia += x; else off += x;
-                }
-            s_done = off <= 1e-30 * dia;
-        }
+        if (tid == 0) s_rot = 0;
         __syncthreads();
-        if (s_done) break;
         for (int round = 0; round < m - 1; ++round) {
             if (tid < m / 2) {
                 auto slot = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + round) % (m - 1); };
@@ -306,7 +312,10 @@ __device__ void jacobi_eig(double *A, double *V, int n)
                 double c = 1.0, s = 0.0;
                 if (q < n) {
                     const double apq = A[p * K + q];
-                    if (apq != 0.0) {
+                    const double thr =
+                        1e-14 * sqrt(fabs(A[p * K + p] * A[q * K + q])) + floor_abs;
+                    if (fabs(apq) > thr) {
+                        s_rot = 1;
                         const double th = (A[q * K + q] - A[p * K + p]) / (2.0 * apq);
                         const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
@@ -341,6 +350,10 @@ __device__ void jacobi_eig(double *A, double *V, int n)
             }
             __syncthreads();
         }
+        // every thread reads the flag before thread 0 clears it again
+        const int rotated = s_rot;
+        __syncthreads();
+        if (!rotated) break;
     }
 }
 
