@@ -9,11 +9,12 @@ eqs. (6)-(7): two pseudo-inverse solves (source and coupling sequences),
 their start vectors and history updates, and the conducting-region update.
 
 The headline value is steps/s with SPE start vectors (window m = 8) replayed
-from a captured HIP graph; ZERO (plain zero-start PCG), PREV and POD
-(20 snapshots, at most 10 modes) run the same steps for comparison.
+from a captured HIP graph; CSPE (the growing basis: SPE with up to 19
+columns), ZERO (plain zero-start PCG), PREV and POD (20 snapshots, at most
+10 modes) run the same steps for comparison.
 Inputs are synthetic (seeded geometry; no benchmark data).
 
-Usage: python bench.py [--steps K] [--warmup W] [--methods spe,pod,prev,zero]
+Usage: python bench.py [--steps K] [--warmup W] [--methods spe,cspe,pod,prev,zero]
                        [--cpu-steps S] [--no-cpu] [--no-probe]
 """
 from __future__ import annotations
@@ -54,6 +55,8 @@ def method_opts(ec, name, rtol, graph_iters=(0, 0)):
     kw = dict(rtol=rtol, maxit=100000, graph_iters=graph_iters)
     if name == "spe":
         return ec.step_opts(ec.SV_SPE, window=8, pod_kmax=8, **kw)
+    if name == "cspe":       # the paper's growing basis: up to 19 columns
+        return ec.step_opts(ec.SV_SPE, window=19, pod_kmax=8, **kw)
     if name == "pod":
         return ec.step_opts(ec.SV_POD, window=20, pod_kmax=10, pod_eps=1e-4, **kw)
     if name == "prev":
@@ -350,7 +353,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--methods", default="spe,pod,prev,zero")
+    ap.add_argument("--methods", default="spe,cspe,pod,prev,zero")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
@@ -477,7 +480,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "nonlinear 48^3 FIT cube, Brauer iron 16^3, coil ramp 1000 "
                                "steps, dt = 0.5 x CFL bound, rtol 1e-8",
-                   "start_vector": {"spe": "SPE window 8", "pod": "POD 20 snapshots <=10 modes",
+                   "start_vector": {"spe": "SPE window 8", "cspe": "SPE growing to 19 columns",
+                                    "pod": "POD 20 snapshots <=10 modes",
                                     "prev": "previous solution", "zero": "zero"}[head],
                    "graph": True},
         "iters_per_step": round(r["iters_per_step"], 3),

@@ -225,6 +225,28 @@ def test_spe_large_window(ec, oracle_mod):
         assert np.linalg.norm(x0 - ref) <= 1e-9 * np.linalg.norm(ref), w
 
 
+def test_cspe_growing_basis(ec, oracle_mod):
+    """The paper's growing basis (fewer than 20 columns, only the newest
+    column added per step): with a 19-column window each push appends one
+    orthogonalised column, the start vector is the projection on all
+    solutions so far, and the 20th push slides the window.  The start vectors
+    agree with the oracle's projection after 1, 6, 12, 13, 19 and 20 pushes
+    (both Cholesky paths: up to 12 columns in registers, beyond in shared
+    memory)."""
+    from oracle.startvec import spe_start
+    G, O, _ = pair(ec, oracle_mod, "small", cap=20)
+    win = [O.kn(synth.random_vector(O.n_pad, O.N, 80 + s)) for s in range(20)]
+    b = O.source(1, 1e-3) + O.kcnT(synth.random_vector(O.n_pad, O.C, 9))
+    seq = ec.SEQ_USER
+    G.history_reset(seq)
+    for i, v in enumerate(win, 1):
+        G.history_push(seq, ec.SV_SPE, 19, G.tensor(v))
+        if i in (1, 6, 12, 13, 19, 20):
+            x0 = G.start_vector(seq, ec.SV_SPE, 19, G.tensor(b)).cpu().numpy()
+            ref = spe_start(O, win[max(0, i - 19):i], b)
+            assert np.linalg.norm(x0 - ref) <= 1e-9 * np.linalg.norm(ref), i
+
+
 def test_spe_gauge_penalty(ec, oracle_mod):
     """A window holding a pure gradient (a null vector of K_n): with the
     grad-div term the start vector is x* itself, as in the oracle; with the
