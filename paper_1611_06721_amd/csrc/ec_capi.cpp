@@ -792,8 +792,9 @@ constexpr int kGraphMaxIters = 4096;
 // convergence).  Eagerly, iterations go out in chunks and the host reads the
 // device done flag of the previous chunk (pinned copy) while the next chunk
 // runs; the first chunk is the previous iteration count of the sequence.
-// want_cap > 0: a captured solve issues at most that many iteration kernels
-// (with the tail, the last of them is the tail).
+// want_cap > 0: where the tail is available, a captured solve issues at most
+// that many iteration kernels, the last of them the tail (also without a
+// sequence budget).
 template <typename T>
 static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hintable, int *n_issued,
                           bool *fin_done = nullptr, int want_cap = 0)
@@ -806,8 +807,8 @@ static int32_t cg_iterate(ec_problem *h, const CgArgs<T> &a, int seq, bool hinta
         // the sequence budget caps the FP64 solve or each inner FP32 pass of
         // a refined solve; the tail finishes either
         int want = h->graph_iters[seq];
-        if (want > 0 && want_cap > 0) want = std::min(want, want_cap);
         const int tblocks = std::is_same<T, double>::value ? h->tail_blocks : h->tail_blocks_f;
+        if (want_cap > 0 && tblocks > 0) want = want > 0 ? std::min(want, want_cap) : want_cap;
         const bool tail = want > 0 && want < maxit && tblocks > 0;
         if (want > 0) budget = std::min(budget, want);
         // with the tail, it runs the last budgeted iteration itself (the same

@@ -577,6 +577,19 @@ def test_refined_graph_starved_budget_equals_eager(ec, oracle_mod):
     c = G2.counters()
     assert c["worst_status"] == 0 and c["steps"] == 15
     assert np.array_equal(A2.cpu().numpy(), A1.cpu().numpy())
+    # no budget: the first pass issues inner_maxit kernels, later passes one
+    # kernel and the tail
+    G3 = ec.Problem(wl, window_cap=8)
+    A3 = G3.zeros()
+    G3.set_state(A3, rtol=1e-10)
+    G3.run(A3, 0, 10, dt, opts)
+    G3.counters_reset()
+    g3 = G3.graph_capture(A3, dt, opts)
+    for _ in range(15):
+        g3.launch()
+    c3 = G3.counters()
+    assert c3["worst_status"] == 0 and c3["steps"] == 15
+    assert np.array_equal(A3.cpu().numpy(), A1.cpu().numpy())
 
 
 # ------------------------------------------------ 2.5D (LDS-staged) PCG kernel
