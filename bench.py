@@ -15,7 +15,8 @@ columns), ZERO (plain zero-start PCG), PREV and POD (20 snapshots, at most
 Inputs are synthetic (seeded geometry; no benchmark data).
 
 Usage: python bench.py [--steps K] [--warmup W] [--methods spe,cspe,pod,prev,zero]
-                       [--cpu-steps S] [--no-cpu] [--no-probe]
+                       [--cpu-steps S] [--no-cpu] [--no-probe] [--no-c3] [--no-adjoint]
+                       [--no-batch] [--c3-check-steps S]
 """
 from __future__ import annotations
 
@@ -34,8 +35,15 @@ COPY_BYTES = 512 << 20
 METRIC = "Euler steps/sec at rel. residual 1e-8; PCG iters/step; SpMV HBM GB/s"
 
 
-# captured PCG launches per solve beyond the warm-up's upper quartile
+# captured PCG launches per solve beyond the warm-up median
 BUDGET_MARGIN = 0
+# at most this many iteration kernels per captured solve on grids that run the
+# node-parallel iteration; a longer solve continues in the persistent tail,
+# whose iterations cost about as much as launched ones there (48^3: CPL
+# budgets of 6 to 17 within 1 %), so a short warm-up (whose last steps still
+# need many iterations: the window is not yet full) cannot make every replay
+# issue dozens of kernels that find the solve finished
+BUDGET_CAP_NODE = 12
 
 
 def log(*a):
@@ -64,14 +72,14 @@ def method_opts(ec, name, rtol, graph_iters=(0, 0)):
     return ec.step_opts(ec.SV_ZERO, window=1, **kw)
 
 
-def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
+def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None, cap=None):
     """`warmup` eager steps from rest (not timed; they also fill the start-vector
     histories), then `steps` replays of the captured step, continuing the same
     run, timed with events on the library's stream.  Each captured solve issues
     a fixed number of PCG iteration kernels, sized from the second half of the
-    warm-up; a solve that needs more continues in one persistent launch.  If a
-    solve still fails (maxit), the measurement is repeated with twice the
-    budget."""
+    warm-up and capped at `cap` (None: no cap); a solve that needs more
+    continues in one persistent launch.  If a solve still fails (maxit), the
+    measurement is repeated with twice the budget."""
     import numpy as np
     if make_opts is None:
         def make_opts(graph_iters=(0, 0)):
@@ -93,9 +101,11 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
             # that finds the solve finished (a budget of one, the tail
             # deciding, measured about 1 % slower: the tail's blocks hold a
             # CU's registers while the other branch's pushes run)
-            h = warmup // 2
+            h = min(warmup // 2, max(warmup - 2, 0))
             med = [int(np.median(its[2 * h + q::2])) for q in (0, 1)]
             budgets = [max(1, v + BUDGET_MARGIN) if v > 0 else 2 for v in med]
+            if cap:
+                budgets = [min(b, cap) for b in budgets]
         G.counters_reset()
         graph = G.graph_capture(A, dt, make_opts(tuple(budgets)))
         torch.cuda.synchronize()
@@ -108,7 +118,7 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
         e1.synchronize()
         ms = e0.elapsed_time(e1)
         c = G.counters()
-        del graph
+        graph.close()
         if c["worst_status"] == 0 and c["steps"] == steps:
             break
         log(f"[bench] {name}: budget {budgets} insufficient (status {c['worst_status']}), retry")
@@ -126,33 +136,43 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None):
     }, A
 
 
-def precision_c3(ec, torch, steps, warmup, rtol=1e-8, N=128):
+def precision_c3(ec, torch, steps, warmup, check_steps, rtol=1e-8, N=128):
     """FP64 PCG vs FP32 inner PCG in the FP64 residual loop on the 128^3
     Brauer grid, SPE m = 8, the same captured-step measurement as the
-    headline; the relative difference between the two final states is
-    reported (it includes the gradient part a_n may pick up)."""
+    headline (with its own `warmup`).  The first `check_steps` steps from
+    rest are also run eagerly in both precisions and their states kept on the
+    host: the CPU leg compares them with the FP64 oracle step by step."""
     import synth
     G = ec.Problem(synth.nonlinear(N), window_cap=8)
     lam = G.cfl(iters=40, rtol=1e-10)
     dt = 0.5 * 2.0 / lam
-    out, finals = {}, {}
+    out, finals, traj = {}, {}, {}
     for prec, tag in ((ec.PREC_FP64, "fp64"), (ec.PREC_FP32_REFINED, "fp32_refined")):
         def make_opts(graph_iters=(0, 0), prec=prec):
             return ec.step_opts(ec.SV_SPE, window=8, rtol=rtol, maxit=100000, precision=prec,
                                 inner_rtol=1e-5, inner_maxit=200, outer_max=4,
                                 graph_iters=graph_iters)
+        if check_steps > 0:
+            A = G.zeros()
+            G.set_state(A, rtol=rtol)
+            rec = []
+            for m in range(1, check_steps + 1):
+                G.step(A, m, dt, make_opts())
+                rec.append(A.cpu().numpy())
+            traj[tag] = rec
         r, A = run_method(ec, torch, G, "spe", dt, steps, warmup, rtol, make_opts)
         out[tag] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
         finals[tag] = A.clone()
         log(f"[bench] 128^3 {tag}: {r['steps_per_s']:.1f} steps/s, {r['iters_per_step']:.2f} iters/step")
     a64, a32 = finals["fp64"], finals["fp32_refined"]
-    out["final_state_rel_diff"] = float((a32 - a64).norm() / a64.norm())
-    out["workload"] = f"nonlinear {N}^3, {steps} captured steps after {warmup} warm-up, SPE m=8"
+    out["final_state_rel_diff_fp32_vs_fp64"] = float((a32 - a64).norm() / a64.norm())
+    out["workload"] = (f"nonlinear {N}^3, {steps} captured steps after {warmup} eager warm-up "
+                       f"steps, SPE m=8, rtol {rtol:g}")
     out["speedup_fp32_refined"] = round(out["fp32_refined"]["steps_per_s"] /
                                         out["fp64"]["steps_per_s"], 3)
-    del G
+    G.close()
     torch.cuda.empty_cache()
-    return out
+    return out, {"N": N, "dt": dt, "rtol": rtol, "traj": traj}
 
 
 def adjoint_c5(ec, torch, steps=500, every=50, N=64, rtol=1e-8, check_steps=100):
@@ -201,13 +221,14 @@ def adjoint_c5(ec, torch, steps=500, every=50, N=64, rtol=1e-8, check_steps=100)
     def L(sigma, k1):
         G.set_material(1, sigma, k1, m.k2, m.k3)
         return float(G.adjoint_forward(G.zeros(), check_steps, dt, every, o12, wsc).item())
-    h = 1e-4
+    h = 1e-6
     fd_s = (L(m.sigma * (1 + h), m.k1) - L(m.sigma * (1 - h), m.k1)) / (2 * h * m.sigma)
     fd_k = (L(m.sigma, m.k1 * (1 + h)) - L(m.sigma, m.k1 * (1 - h))) / (2 * h * m.k1)
     out["fd_check"] = {"steps": check_steps, "rtol": 1e-12, "h": h,
                        "rel_err_dsigma": float(abs(gc[0] - fd_s) / abs(fd_s)),
                        "rel_err_dk1": float(abs(gc[1] - fd_k) / abs(fd_k))}
-    del G, wsc
+    del wsc
+    G.close()
     torch.cuda.empty_cache()
     return out
 
@@ -274,6 +295,8 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
         e1.synchronize()
         ms = e0.elapsed_time(e1)
         cs = [p.counters() for p in probs]
+        for g in graphs:
+            g.close()
         del graphs
         iters = sum(c["iters_src"] + c["iters_cpl"] for c in cs)
         out[mode] = {"instance_steps_per_s": round(count * steps / (ms * 1e-3), 1),
@@ -285,6 +308,9 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
         log(f"[bench] batch {mode}: {out[mode]['instance_steps_per_s']} instance-steps/s")
     out["speedup_batched"] = round(out["batched_graph"]["instance_steps_per_s"] /
                                    out["per_instance_graphs"]["instance_steps_per_s"], 3)
+    B.close()
+    for p in probs:
+        p.close()
     del B, probs
     torch.cuda.empty_cache()
     return out
@@ -331,21 +357,117 @@ def traffic_record(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(steps, dt):
-    """The oracle (plain FP64 C, zero-start CG) on the host cores: the first
-    `steps` steps of the same workload (about 20 s at 300 steps)."""
+def host_info():
+    """lscpu model, sockets and physical cores of the host, and the CPU share
+    this process may use (the GPU machine grants 16 threads per GPU)."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = dict(l.split(":", 1) for l in txt.splitlines() if ":" in l)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "1"))
+        cps = int(kv.get("Core(s) per socket", "0"))
+        info["sockets"] = sockets
+        info["physical_cores"] = sockets * cps
+        info["threads_per_core"] = int(kv.get("Thread(s) per core", "1"))
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except OSError:
+        info["affinity_cpus"] = os.cpu_count()
+    return info
+
+
+def triad_gbs(threads, n=1 << 26, reps=5):
+    """Host STREAM-style triad a = b + s c over 3 x 512 MiB FP64 arrays with
+    torch's CPU kernels on `threads` threads (24 B per element)."""
+    import torch
+    old = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    b = torch.rand(n, dtype=torch.float64)
+    c = torch.rand(n, dtype=torch.float64)
+    a = torch.empty_like(b)
+    best = 1e30
+    for _ in range(reps):
+        t = time.perf_counter()
+        torch.add(b, c, alpha=3.0, out=a)
+        best = min(best, time.perf_counter() - t)
+    torch.set_num_threads(old)
+    del a, b, c
+    return round(24.0 * n / best / 1e9, 1)
+
+
+def cpu_baseline(steps, warmup, dt, c3_ref=None, single_steps=20):
+    """The oracle (plain FP64 C + OpenMP, zero-start CG, as it stands) on the
+    host: steps warmup+1 .. warmup+steps of the headline workload (the steps
+    the GPU line times; the state at `warmup` comes from an untimed oracle
+    run) on the process's CPU share, and the first `single_steps` of them on
+    one thread; lscpu and a triad probe beside the numbers.  With c3_ref it
+    also runs the oracle over the first steps of the 128^3 run and returns the
+    per-step error of the GPU's FP64 and FP32-refined states against it."""
+    import numpy as np
     import oracle
     import synth
-    threads = min(os.cpu_count() or 1, 16)
-    oracle.set_threads(threads)
+    hi = host_info()
+    share = max(1, min(hi.get("affinity_cpus") or 16, 16))
     O = oracle.Problem(synth.nonlinear(48))
-    t = time.time()
-    O.run(dt, steps, rtol=1e-8)
-    el = time.time() - t
-    return {"value": steps / el, "unit": "steps/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
-            "sample": f"steps 1..{steps} of the 48^3 nonlinear run, zero-start CG, "
-                      f"{el:.1f} s wall"}
+
+    def timed(threads, n):
+        oracle.set_threads(threads)
+        A0, sc0 = None, None
+        if warmup > 0:
+            A0, sc0, *_ = O.run(dt, warmup, rtol=1e-8)
+        t = time.time()
+        O.run(dt, n, rtol=1e-8, A=A0, sc=sc0, m0=warmup)
+        return time.time() - t, oracle.get_threads()
+
+    el, used = timed(share, steps)
+    el1, _ = timed(1, min(single_steps, steps))
+    out = {"value": steps / el, "unit": "steps/s", "cores": used, "kind": "oracle",
+           "sample": f"steps {warmup + 1}..{warmup + steps} of the 48^3 nonlinear run (the GPU "
+                     f"line's timed steps), zero-start CG at rtol 1e-8, {el:.1f} s wall on "
+                     f"{used} threads",
+           "single_thread": {"value": min(single_steps, steps) / el1, "unit": "steps/s",
+                             "cores": 1,
+                             "sample": f"steps {warmup + 1}..{warmup + min(single_steps, steps)}"
+                                       f", {el1:.1f} s wall"},
+           "host": hi,
+           "triad_GBs": {"threads_%d" % used: triad_gbs(used), "threads_1": triad_gbs(1)}}
+    if c3_ref and c3_ref["traj"]:
+        oracle.set_threads(share)
+        wl = synth.nonlinear(c3_ref["N"])
+        P = oracle.Problem(wl)
+        n = min(len(v) for v in c3_ref["traj"].values())
+        t = time.time()
+        _, _, rec, its, itc = P.run(c3_ref["dt"], n, rtol=c3_ref["rtol"], rec_every=1)
+        el3 = time.time() - t
+        C, N = P.C, P.N
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        errs = {}
+        for tag, tr in c3_ref["traj"].items():
+            e = {"a_c": [], "B": [], "Kn_an": [], "a_n": [], "A": []}
+            for m in range(n):
+                g, o = tr[m], rec[m]
+                e["a_c"].append(rel(g[C], o[C]))
+                e["B"].append(rel(P.curl(g), P.curl(o)))
+                e["Kn_an"].append(rel(P.kn(np.where(N, g, 0.0)), P.kn(np.where(N, o, 0.0))))
+                e["a_n"].append(rel(g[N], o[N]))
+                e["A"].append(rel(g, o))
+            errs[tag] = {k: [float("%.3g" % x) for x in v] for k, v in e.items()}
+        out["precision_128_vs_oracle"] = {
+            "steps": n, "rtol": c3_ref["rtol"],
+            "note": "relative 2-norm error per step against the FP64 oracle (zero-start CG at "
+                    "the same rtol); a_n also holds a gauge (gradient) part that the "
+                    "gauge-invariant a_c, B = C a and K_n a_n do not see",
+            "errors": errs,
+            "oracle_steps_per_s": round(n / el3, 4),
+            "oracle_iters_per_step": float(np.mean(its + itc))}
+    return out
 
 
 def main():
@@ -354,11 +476,17 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--methods", default="spe,cspe,pod,prev,zero")
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps timed on the host (default: the GPU's timed steps, "
+                         "at most 300)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 128^3 FP64 / FP32-refined runs")
     ap.add_argument("--c3-steps", type=int, default=200)
+    ap.add_argument("--c3-warmup", type=int, default=20,
+                    help="eager warm-up steps of the 128^3 runs (their own, not --warmup)")
+    ap.add_argument("--c3-check-steps", type=int, default=8,
+                    help="first steps of the 128^3 run compared with the FP64 oracle per step")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 64^3 adjoint runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch runs")
     ap.add_argument("--budget-margin", type=int, default=None,
@@ -405,7 +533,8 @@ def main():
     results = {}
     for name in args.methods.split(","):
         log(f"[bench] method {name}: warmup {args.warmup}, {args.steps} steps")
-        r, _ = run_method(ec, torch, G, name, dt, args.steps, args.warmup, rtol)
+        r, _ = run_method(ec, torch, G, name, dt, args.steps, args.warmup, rtol,
+                          cap=BUDGET_CAP_NODE)
         results[name] = r
         log(f"[bench] {name}: {r['steps_per_s']:.1f} steps/s, {r['iters_per_step']:.2f} iters/step")
     head = "spe" if "spe" in results else next(iter(results))
@@ -422,6 +551,7 @@ def main():
                 "traffic": traffic, "kernel": "k_cg_iter<double> (one PCG iteration)",
                 "avg_us": round(cg_us, 3), "bytes_per_launch": cg_bytes}
     extra = {}
+    G.close()
     del G
     torch.cuda.empty_cache()
 
@@ -441,13 +571,14 @@ def main():
                                       "achieved_GBs": round(80.0 * nn / (us * 1e-6) / 1e9, 1),
                                       "frac": round(80.0 * nn / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
                                       "traffic": traffic_record("k_cg_iter25", f"{Np}^3")}
+            Gp.close()
             del Gp
             torch.cuda.empty_cache()
             log(f"[bench] probe {Np}^3: cg iteration {us:.1f} us")
 
-    c3 = None
+    c3, c3_ref = None, None
     if not args.no_c3:
-        c3 = precision_c3(ec, torch, args.c3_steps, args.warmup)
+        c3, c3_ref = precision_c3(ec, torch, args.c3_steps, args.c3_warmup, args.c3_check_steps)
 
     adj = None
     if not args.no_adjoint:
@@ -461,8 +592,12 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args.cpu_steps, dt)
-        log(f"[bench] cpu oracle: {cpu['value']:.3f} steps/s on {cpu['cores']} threads")
+        cpu_steps = args.cpu_steps if args.cpu_steps else min(args.steps, 300)
+        cpu = cpu_baseline(cpu_steps, args.warmup, dt, c3_ref)
+        log(f"[bench] cpu oracle: {cpu['value']:.3f} steps/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.3f} on one")
+        if c3 is not None and "precision_128_vs_oracle" in cpu:
+            c3["vs_oracle"] = cpu.pop("precision_128_vs_oracle")
 
     r = results[head]
     line = {
@@ -480,6 +615,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "nonlinear 48^3 FIT cube, Brauer iron 16^3, coil ramp 1000 "
                                "steps, dt = 0.5 x CFL bound, rtol 1e-8",
+                   "timed_steps": f"m = {args.warmup + 1}..{args.warmup + args.steps} "
+                                  f"(after {args.warmup} eager warm-up steps from rest)",
                    "start_vector": {"spe": "SPE window 8", "cspe": "SPE growing to 19 columns",
                                     "pod": "POD 20 snapshots <=10 modes",
                                     "prev": "previous solution", "zero": "zero"}[head],

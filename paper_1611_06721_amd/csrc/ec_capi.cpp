@@ -336,6 +336,13 @@ extern "C" int32_t ec_create(const ec_grid *grid, const ec_materials *mat, const
 
 extern "C" int32_t ec_destroy(ec_handle h)
 {
+    if (!h) return EC_OK;
+    // drain the problem's streams before their events, the side stream and
+    // the pinned polling buffer go (work still queued may signal them)
+    if (h->bound) {
+        (void)hipStreamSynchronize(h->st);
+        if (h->side) (void)hipStreamSynchronize(h->side);
+    }
     delete h;
     return EC_OK;
 }
@@ -2424,6 +2431,8 @@ extern "C" int32_t ec_graph_destroy(void *graph_exec)
 {
     if (graph_exec) {
         GraphBox *g = (GraphBox *)graph_exec;
+        // a replay may still be running on the problem's stream
+        if (g->h && g->h->bound) (void)hipStreamSynchronize(g->h->st);
         (void)hipGraphExecDestroy(g->ex);
         delete g;
     }

@@ -4,6 +4,7 @@ from __future__ import annotations
 
 import contextlib
 import ctypes as C
+import sys
 
 import numpy as np
 import torch
@@ -98,11 +99,21 @@ class Problem:
             if cur.cuda_stream != self.stream.cuda_stream:
                 cur.wait_stream(self.stream)
 
-    def __del__(self):
+    def close(self):
+        """Destroy the handle after the library's stream has drained (the
+        workspace tensor is released with this object).  Graphs and batches
+        that use the problem must be closed first."""
         h = getattr(self, "h", None)
         if h is not None and getattr(self, "lib", None) is not None:
+            self.stream.synchronize()
             self.lib.ec_destroy(h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        # at interpreter exit the HIP runtime (or a profiler wrapped around
+        # it) may already be gone: leave the process teardown to free it
+        if not sys.is_finalizing():
+            self.close()
 
     def zeros(self):
         return torch.zeros(self.n_pad, dtype=torch.float64, device=self.device)
@@ -257,10 +268,15 @@ class Graph:
         """Replay without stream hand-offs (the caller synchronises)."""
         L.check(self.lib.ec_graph_launch(self.g, C.c_void_p(self.prob.stream.cuda_stream)))
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "g", None):
+            self.prob.stream.synchronize()
             self.lib.ec_graph_destroy(self.g)
-            self.g = None
+        self.g = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
 
 class Batch:
@@ -322,8 +338,13 @@ class Batch:
                                                C.byref(f), C.byref(us)))
         return f.value, us.value
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "b", None):
+            self.stream.synchronize()
             self.lib.ec_batch_destroy(self.b)
-            self.b = None
+        self.b = None
+
+    def __del__(self):
+        if not sys.is_finalizing():
+            self.close()
 
