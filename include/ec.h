@@ -50,7 +50,7 @@ enum {
     EC_ERR_HIP = -2,            /* HIP runtime failure */
     EC_ERR_NOT_CONVERGED = -3,  /* PCG reached maxit */
     EC_ERR_BREAKDOWN = -4,      /* p^T K_n p <= 0 with r != 0 */
-    EC_ERR_CFL = -5,            /* dt above the stability bound (eq. 8) */
+    EC_ERR_CFL = -5,            /* dt above the bound 2/lambda_max of the last ec_cfl (eq. 8) */
     EC_ERR_NONFINITE = -6,      /* NaN or Inf in a solve or in the state */
     EC_ERR_STATE = -7,          /* call out of order (not bound, ...) */
     EC_ERR_SINGULAR_PROJ = -8   /* projected SPE/POD matrix not SPD: zero start used */
@@ -272,7 +272,11 @@ int32_t ec_counters_reset(ec_handle h);
 
 /* Largest eigenvalue of M_c^{-1} K_S(a_c) (eq. 8) by the power method with
  * `power_iters` iterations (each one K_n^+ solve), reluctivity frozen at A.
- * Synchronises; result in *lambda_max (host). */
+ * Synchronises; result in *lambda_max (host).  The handle keeps the value:
+ * from then on every step (ec_step, ec_run, captures, batch steps, the
+ * adjoint's forward pass) with dt * lambda_max > 2, outside the explicit
+ * Euler bound of eq. 8, fails with EC_ERR_CFL before any work is enqueued.
+ * ec_bind and ec_set_material clear it (no check until the next ec_cfl). */
 int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, double rtol,
                double *lambda_max);
 

@@ -53,7 +53,8 @@ __device__ __forceinline__ double lane_read(double v, int l)
 // trailing lower triangle updated.  bad: a pivot not positive relative to
 // the largest diagonal entry.
 template <int NM>
-__device__ __forceinline__ void chol_factor_regs(const double *H, int n, double (&a)[NM], int &bad)
+__device__ __forceinline__ void chol_factor_regs(const double *H, int n, double (&a)[NM], int &bad,
+                                                 double hscale)
 {
     const int r = threadIdx.x;
 #pragma unroll
@@ -65,6 +66,7 @@ __device__ __forceinline__ void chol_factor_regs(const double *H, int n, double 
     double dmax = r < n ? fabs(dg) : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    dmax = fmax(dmax, hscale);
     bad = 0;
 #pragma unroll
     for (int j = 0; j < NM; ++j) {
@@ -93,7 +95,7 @@ __device__ __forceinline__ void chol_factor_regs(const double *H, int n, double 
 // largest diagonal entry.  y: n values (shared memory).
 template <int NM>
 __device__ __forceinline__ void chol_wave(const double *H, double *y, const double *gv, int n,
-                                          int *bad_out)
+                                          int *bad_out, double hscale)
 {
     const int r = threadIdx.x;
     double a[NM];
@@ -107,6 +109,7 @@ __device__ __forceinline__ void chol_wave(const double *H, double *y, const doub
     double dmax = r < n ? fabs(dg) : 0.0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    dmax = fmax(dmax, hscale);
     int bad = 0;
 #pragma unroll
     for (int j = 0; j < NM; ++j) {
@@ -158,7 +161,7 @@ __device__ __forceinline__ void chol_wave(const double *H, double *y, const doub
 // (leading dimension K), serial parts on thread 0, block barriers between
 // the steps.
 __device__ __noinline__ int chol_shared(const double *H, double *L, double *y, const double *gv,
-                                        int n)
+                                        int n, double hscale)
 {
     __shared__ int s_bad;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -168,7 +171,7 @@ __device__ __noinline__ int chol_shared(const double *H, double *L, double *y, c
         L[r * K + c] = H[r * K + c];
     }
     __syncthreads();
-    double dmax = 0.0;
+    double dmax = hscale;
     for (int i = 0; i < n; ++i) dmax = fmax(dmax, fabs(L[i * K + i]));
     for (int j = 0; j < n; ++j) {
         if (tid == 0) {
@@ -208,11 +211,12 @@ __device__ __noinline__ int chol_shared(const double *H, double *L, double *y, c
 // Windows of up to kCholReg columns (the usual case) factor in registers on
 // wave 0; larger ones in shared memory L.
 constexpr int kCholReg = 12;
-__device__ bool chol_solve(const double *H, double *L, double *y, const double *gv, int n)
+__device__ bool chol_solve(const double *H, double *L, double *y, const double *gv, int n,
+                           double hscale)
 {
     __shared__ int s_bad;
-    if (n > kCholReg) return chol_shared(H, L, y, gv, n) == 0;
-    if (threadIdx.x < 64) chol_wave<kCholReg>(H, y, gv, n, &s_bad);
+    if (n > kCholReg) return chol_shared(H, L, y, gv, n, hscale) == 0;
+    if (threadIdx.x < 64) chol_wave<kCholReg>(H, y, gv, n, &s_bad, hscale);
     __syncthreads();
     return s_bad == 0;
 }
@@ -263,7 +267,7 @@ __device__ __forceinline__ void chol_store(SeqDev *sq)
     if (sq->L_ver == hv || n < 1 || n > kCholReg) return;
     double a[kCholReg];
     int bad;
-    chol_factor_regs<kCholReg>(sq->H, n, a, bad);
+    chol_factor_regs<kCholReg>(sq->H, n, a, bad, sq->hscale);
     const int r = threadIdx.x;
 #pragma unroll
     for (int c = 0; c < kCholReg; ++c)
@@ -375,7 +379,7 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
         __syncthreads();
         bool good = k > 0;
         if (good && !chol_solve_stored(sq, Ls, ys, gs, k, &good))
-            good = chol_solve(sq->H, Ls, ys, gs, k);
+            good = chol_solve(sq->H, Ls, ys, gs, k, sq->hscale);
         // entries are independent: one per thread (no chain of dependent
         // global loads and stores on thread 0)
         for (int i = tid; i < K; i += nt) {
@@ -628,7 +632,7 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
         }
         __syncthreads();
         bool good = kp > 0;
-        if (good) good = chol_solve(Ms, Ls, ys, gs, kp);
+        if (good) good = chol_solve(Ms, Ls, ys, gs, kp, sq->hscale);
         if (tid == 0) {
             // z = V_k Sigma_k^-1 y ; x0 = X z ; r0 = b - (K X) z
             for (int l = 0; l < K; ++l) {
@@ -1145,17 +1149,21 @@ void seq_reset(SeqDev *seq, hipStream_t st)
     hipLaunchKernelGGL(k_seq_reset, dim3(1), dim3(256), 0, st, seq);
 }
 
-__global__ void k_seq_config(SeqDev *sq, int method, int cap, int kmax, double eps)
+__global__ void k_seq_config(SeqDev *sq, int method, int cap, int kmax, double eps,
+                             double hscale)
 {
+    sq->hscale = hscale;
     sq->method = method;
     sq->cap = cap;
     sq->pod_kmax = kmax;
     sq->pod_eps = eps;
 }
 
-void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st)
+void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, double hscale,
+                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seq_config, dim3(1), dim3(1), 0, st, seq, method, cap, kmax, eps);
+    hipLaunchKernelGGL(k_seq_config, dim3(1), dim3(1), 0, st, seq, method, cap, kmax, eps,
+                       hscale);
 }
 
 __global__ void k_seq_push_on(SeqDev *sq) { sq->push_on = 1; }

@@ -62,6 +62,9 @@ struct ec_problem {
     // grad-div weight of the SPE projection: eta0 = half the mean diagonal of
     // K_n on edges off the conductor, scaled by the caller's factor
     double eta0 = 0.0, gauge_rel = 1.0;
+    // largest eigenvalue of M_c^{-1} K_S from the last ec_cfl (0: none since
+    // bind or the last material change); steps with dt above 2 / cfl_lam fail
+    double cfl_lam = 0.0;
     double dep_tol = kDepTol;    // SPE linear-independence threshold (relative)
     double seq_eta[EC_NSEQ] = {};  // grad-div weight the stored SPE matrix was built with
     // per-sequence iteration budget of the solves being captured (0 = maxit)
@@ -449,6 +452,12 @@ static int choose_blocks(ec_problem *h)
     return (int)std::max<int64_t>(b, 8);
 }
 
+// largest diagonal entry of K_n (the Jacobi diagonal of the x, y, z edges)
+static double kn_diag_max(const ec_problem *h)
+{
+    return 1.0 / std::min(h->g.dinv[0], std::min(h->g.dinv[1], h->g.dinv[2]));
+}
+
 extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64_t bytes,
                            int32_t window_cap)
 {
@@ -488,7 +497,7 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
     c.worst = EC_OK;
     HIP_TRY(h, hipMemcpyAsync(h->ctrl_d, &c, sizeof c, hipMemcpyHostToDevice, st));
     for (int s = 0; s < EC_NSEQ; ++s) {
-        seq_config(h->seq_d + s, EC_SV_SPE, window_cap, window_cap, 1e-4, st);
+        seq_config(h->seq_d + s, EC_SV_SPE, window_cap, window_cap, 1e-4, kn_diag_max(h), st);
         seq_reset(h->seq_d + s, st);
         h->seq_method[s] = -1;
         h->hint[s] = 16;
@@ -501,6 +510,7 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
         if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     h->pending_meth = -1;
+    h->cfl_lam = 0.0;
     h->tiles = (int)((h->S + kTile - 1) / kTile);
     h->node_blocks = choose_blocks(h);
     h->cg_blocks = plan_25(h, false) ? h->grid25 : h->node_blocks;
@@ -529,7 +539,7 @@ static void seq_ensure(ec_problem *h, int seq, int method, int window, int kmax,
     if (h->seq_method[seq] == method && h->seq_win[seq] == window && h->seq_kmax[seq] == kmax &&
         h->seq_eps[seq] == eps)
         return;
-    seq_config(h->seq_d + seq, method, window, kmax, eps, h->st);
+    seq_config(h->seq_d + seq, method, window, kmax, eps, kn_diag_max(h), h->st);
     // the POD truncation parameters act on the next start vector only; a new
     // method or window starts a new history
     if (h->seq_method[seq] != method || h->seq_win[seq] != window) seq_reset(h->seq_d + seq, h->st);
@@ -1325,6 +1335,10 @@ static int32_t check_step_args(ec_problem *h, double dt, const double *A, const 
 {
     if (!aligned(A) || !o) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(h, EC_ERR_ARG, "dt must be positive");
+    if (h->cfl_lam > 0.0 && dt * h->cfl_lam > 2.0)
+        return fail(h, EC_ERR_CFL,
+                    "dt %.6g above the explicit Euler bound 2/lambda_max = %.6g of the last "
+                    "ec_cfl (eq. 8)", dt, 2.0 / h->cfl_lam);
     const int m = o->start_method;
     if (m < EC_SV_ZERO || m > EC_SV_POD) return fail(h, EC_ERR_ARG, "unknown start method");
     if ((m == EC_SV_SPE || m == EC_SV_POD) &&
@@ -1478,6 +1492,7 @@ extern "C" int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, dou
         for (int t = 0; t < h->nc; ++t) v[t] = gv[t] * h->minv[t];
     }
     *lambda_max = lam;
+    if (std::isfinite(lam) && lam > 0.0) h->cfl_lam = lam;
     return launch_check(h, "cfl");
 }
 
@@ -1522,6 +1537,7 @@ extern "C" int32_t ec_set_material(ec_handle h, int32_t mat_id, const ec_materia
     if (!(m->sigma > 0) || !std::isfinite(m->sigma) || !(m->k1 >= 0) || !std::isfinite(m->k1) ||
         !std::isfinite(m->k2) || !(m->k3 > 0) || !std::isfinite(m->k3))
         return fail(h, EC_ERR_ARG, "need sigma > 0, k1 >= 0, k3 > 0 and finite k2");
+    h->cfl_lam = 0.0;   // the bound of eq. 8 moves with sigma and nu
     h->mats.sig[mat_id] = m->sigma;
     h->mats.k1[mat_id] = m->k1;
     h->mats.k2[mat_id] = m->k2;

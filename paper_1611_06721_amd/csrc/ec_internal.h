@@ -54,6 +54,11 @@ struct SeqDev {
     int pad1;
     double xnorm, rho, pod_info, r0_rel;
     double pod_eps;
+    // largest diagonal entry of K_n: the projected matrices are U^T K_n U (plus
+    // the grad-div term) for unit-norm columns, so a Cholesky pivot at or below
+    // 1e-14 of max(hscale, largest diagonal of the matrix) marks it singular
+    // (a window of null vectors alone has a tiny diagonal of its own)
+    double hscale;
     int pod_kmax, pad2;
     double s[kMaxWin + 1];
     double H[kMaxWin * kMaxWin];
@@ -356,7 +361,10 @@ void refine_decide(const double *part, int blocks, Ctrl *ctrl, int pass, int out
 void refine_update(double *x, const float *d, const Ctrl *ctrl, int64_t n, hipStream_t st);
 void refine_final(double *x, const Ctrl *ctrl, int64_t n, hipStream_t st);
 void refine_reset(Ctrl *ctrl, hipStream_t st);
-void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, hipStream_t st);
+// hscale: the largest diagonal entry of K_n (scale of the projected
+// matrices, whose basis columns have unit norm)
+void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, double hscale,
+                hipStream_t st);
 // an explicit history push (not after a solve): the next push is not skipped
 void seq_push_on(SeqDev *seq, hipStream_t st);
 void negate(const double *x, double *y, int64_t n, hipStream_t st);
