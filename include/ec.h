@@ -389,6 +389,29 @@ int32_t ec_graph_capture_step(ec_handle h, double dt, double *A, const ec_step_o
 int32_t ec_graph_launch(void *graph_exec, void *hip_stream);
 int32_t ec_graph_destroy(void *graph_exec);
 
+/* Allocation-free PCG solve, for callers that cannot allocate device
+ * memory or take a workspace of their own: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It is ec_solve's
+ * FP64 Jacobi-PCG of K_n x = b (eq. 9) with method EC_SV_ZERO (x0 = 0) or
+ * EC_SV_PREV (x holds the start), same kernels and results, but its seven
+ * iteration vectors, control records and block partials live in a static
+ * device array of EC_STATIC_SCRATCH_BYTES in the library (one per GPU,
+ * held until the process ends) instead of the handle's workspace.  The
+ * grid is limited by that array: n_padded at most EC_STATIC_MAX_NPAD
+ * (e.g. 72^3 cells); a larger handle gets EC_ERR_ARG, as do other methods,
+ * FP32_REFINED precision or unaligned pointers.  b, x (device, padded) and
+ * dev_info (device, may be NULL) are the caller's; the handle must be bound
+ * (its tables and stream are used; its counters are not updated).  No
+ * hipMalloc, hipFree or allocating call is made.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (several streams,
+ * threads or handles) race; calls in stream order do not.  Asynchronous
+ * like ec_solve (eager calls poll the device done flag; under capture the
+ * solve budget and the persistent tail apply as in a captured step). */
+#define EC_STATIC_SCRATCH_BYTES (64ll << 20)
+#define EC_STATIC_MAX_NPAD 1195904
+int32_t ec_solve_static(ec_handle h, int32_t method, const double *b, double *x,
+                        const ec_solve_opts *opts, ec_solve_info *dev_info);
+
 /* Message of the last failure on h (or of the last ec_create if h = NULL). */
 const char *ec_last_error(ec_handle h);
 

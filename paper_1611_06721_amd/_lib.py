@@ -20,6 +20,7 @@ SV_ZERO, SV_PREV, SV_SPE, SV_POD = 0, 1, 2, 3
 PREC_FP64, PREC_FP32_REFINED = 0, 1
 OP_KN, OP_KCN_T, OP_KC_KCN = 0, 1, 2
 MAX_WINDOW = 20
+STATIC_MAX_NPAD = 1195904
 
 STATUS_NAMES = {0: "OK", -1: "ARG", -2: "HIP", -3: "NOT_CONVERGED", -4: "BREAKDOWN",
                 -5: "CFL", -6: "NONFINITE", -7: "STATE", -8: "SINGULAR_PROJ"}
@@ -116,6 +117,7 @@ SIGNATURES = {
                                           C.POINTER(C.c_void_p)]),
     "ec_graph_launch": (C.c_int32, [_P, _P]),
     "ec_graph_destroy": (C.c_int32, [_P]),
+    "ec_solve_static": (C.c_int32, [_H, C.c_int32, _P, _P, C.POINTER(SolveOpts), _P]),
     "ec_last_error": (C.c_char_p, [_H]),
 }
 

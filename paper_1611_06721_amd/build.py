@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libec.so")
-SOURCES = ["ec_stencil.hip", "ec_basis.hip", "ec_update.hip", "ec_adjoint.hip", "ec_capi.cpp"]
+SOURCES = ["ec_stencil.hip", "ec_basis.hip", "ec_update.hip", "ec_adjoint.hip", "ec_static.hip",
+           "ec_capi.cpp"]
 ARCH = os.environ.get("EC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -933,6 +933,82 @@ static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const
     return launch_check(h, "cg fin");
 }
 
+// ------------------------------------------------ solve in outside scratch
+// Bytes of device scratch that solve_scratch needs for this handle: the seven
+// PCG vectors (r, w, s double buffered, p), two control records, the block
+// partials and the tail kernel's barrier words.
+int64_t ec::scratch_need(const ec_problem *h)
+{
+    const int64_t ld = align_up(h->npad, 64);
+    return 7 * ld * 8 + align_up(2 * (int64_t)sizeof(CgCtl), kAlign) +
+           align_up(2 * 4 * (int64_t)kMaxBlocks * 8, kAlign) +
+           align_up((int64_t)kBarWords * kBarStride * sizeof(unsigned), kAlign);
+}
+
+// the limit stated in ec.h: the largest n_padded whose scratch fits the array
+constexpr int64_t scratch_need_for(int64_t npad)
+{
+    return 7 * ((npad + 63) / 64 * 64) * 8 + (2 * (int64_t)sizeof(CgCtl) + 255) / 256 * 256 +
+           (2 * 4 * (int64_t)kMaxBlocks * 8 + 255) / 256 * 256 +
+           ((int64_t)kBarWords * kBarStride * (int64_t)sizeof(unsigned) + 255) / 256 * 256;
+}
+static_assert(scratch_need_for(EC_STATIC_MAX_NPAD) <= EC_STATIC_SCRATCH_BYTES &&
+                  scratch_need_for(EC_STATIC_MAX_NPAD + 1) > EC_STATIC_SCRATCH_BYTES,
+              "EC_STATIC_MAX_NPAD does not match the static scratch layout");
+
+hipStream_t ec::bound_stream(const ec_problem *h) { return h && h->bound ? h->st : nullptr; }
+
+// The FP64 PCG of ec_solve (ZERO or PREV start, sequence USER without
+// history) with all of its scratch in the device buffer scr of `bytes`
+// bytes instead of the handle's workspace; the handle's counters are left
+// alone.  lookup: the status of the buffer's address lookup.
+int32_t ec::solve_scratch(ec_problem *h, int32_t method, const double *b, double *x,
+                          const ec_solve_opts *o, ec_solve_info *info, char *scr, int64_t bytes,
+                          hipError_t lookup)
+{
+    NEED_BOUND(h);
+    if (lookup != hipSuccess || !scr)
+        return fail(h, EC_ERR_HIP, "address of the static scratch array: %s",
+                    hipGetErrorString(lookup));
+    flush_pending(h);
+    if (!aligned(b) || !aligned(x) || !o)
+        return fail(h, EC_ERR_ARG, "b, x must be 16-byte aligned device pointers; opts required");
+    if (method != EC_SV_ZERO && method != EC_SV_PREV)
+        return fail(h, EC_ERR_ARG, "the static-scratch solve starts from zero or from x");
+    if (o->precision != EC_PREC_FP64)
+        return fail(h, EC_ERR_ARG, "the static-scratch solve runs FP64 PCG");
+    if (!(o->rtol > 0) || o->maxit < 0) return fail(h, EC_ERR_ARG, "need rtol > 0, maxit >= 0");
+    const int64_t need = scratch_need(h);
+    if (need > bytes)
+        return fail(h, EC_ERR_ARG,
+                    "grid too large for the static scratch: %lld bytes needed (n_padded %lld), "
+                    "%lld available", (long long)need, (long long)h->npad, (long long)bytes);
+    const int64_t ld = align_up(h->npad, 64);
+    CgArgs<double> a = cg64_args(h, EC_SEQ_USER, b, nullptr, x, o, info);
+    double *v = (double *)scr;
+    for (int i = 0; i < 2; ++i) {
+        a.rb[i] = v + (0 + i) * ld;
+        a.wb[i] = v + (2 + i) * ld;
+        a.sb[i] = v + (4 + i) * ld;
+    }
+    a.p = v + 6 * ld;
+    char *q = scr + 7 * ld * 8;
+    a.ctl = (CgCtl *)q;
+    q += align_up(2 * (int64_t)sizeof(CgCtl), kAlign);
+    a.part = (double *)q;
+    q += align_up(2 * 4 * (int64_t)kMaxBlocks * 8, kAlign);
+    a.bar = (unsigned *)q;
+    a.seq = nullptr;
+    a.ctrl = nullptr;
+    cg64_init(h, a, method == EC_SV_ZERO ? START_ZERO : START_X);
+    int issued = 0;
+    bool fin_done = false;
+    int32_t rc = cg_iterate<double>(h, a, EC_SEQ_USER, false, &issued, &fin_done);
+    if (rc) return rc;
+    if (!fin_done) cg_fin<double>(a, issued, h->st);
+    return launch_check(h, "static-scratch solve");
+}
+
 // FP64 residual refinement around FP32 inner PCG solves of K_n d = r
 static int32_t run_refined(ec_problem *h, int seq, const double *b, const double *bscale,
                            double *x, const ec_solve_opts *o, ec_solve_info *info)

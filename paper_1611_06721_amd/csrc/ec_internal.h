@@ -389,4 +389,11 @@ void adj_zero(double *acc, int n, hipStream_t st);
 void gather_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
 void scatter_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
 
+// the PCG solve of ec_solve_static (ec_capi.cpp) and what it needs to know
+int64_t scratch_need(const ec_problem *h);
+hipStream_t bound_stream(const ec_problem *h);
+int32_t solve_scratch(ec_problem *h, int32_t method, const double *b, double *x,
+                      const ec_solve_opts *o, ec_solve_info *info, char *scr, int64_t bytes,
+                      hipError_t lookup);
+
 }  // namespace ec

@@ -139,6 +139,16 @@ class Problem:
                                         C.byref(o), _ptr(info)))
         return x
 
+    def solve_static(self, b, x=None, method=L.SV_ZERO, info=None, **opts):
+        """ec_solve_static: the FP64 PCG of solve() with its scratch in the
+        library's static device array (ZERO or PREV start)."""
+        x = self.zeros() if x is None else x
+        o = solve_opts(**opts)
+        with self._on_stream():
+            self._chk(self.lib.ec_solve_static(self.h, method, _ptr(b), _ptr(x), C.byref(o),
+                                               _ptr(info)))
+        return x
+
     def set_gauge_penalty(self, factor):
         with self._on_stream():
             self._chk(self.lib.ec_set_gauge_penalty(self.h, factor))
