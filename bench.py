@@ -38,12 +38,16 @@ METRIC = "Euler steps/sec at rel. residual 1e-8; PCG iters/step; SpMV HBM GB/s"
 # captured PCG launches per solve beyond the warm-up median
 BUDGET_MARGIN = 0
 # at most this many iteration kernels per captured solve on grids that run the
-# node-parallel iteration; a longer solve continues in the persistent tail,
-# whose iterations cost about as much as launched ones there (48^3: CPL
-# budgets of 6 to 17 within 1 %), so a short warm-up (whose last steps still
-# need many iterations: the window is not yet full) cannot make every replay
-# issue dozens of kernels that find the solve finished
-BUDGET_CAP_NODE = 12
+# node-parallel iteration; a longer solve continues in the persistent tail
+# (an iteration there costs about 7 us more than a launched one at 48^3, a
+# launch that finds the solve finished about 4.5 us), so a short warm-up
+# (whose last steps still need many iterations: the window is not yet full)
+# cannot make every replay issue dozens of kernels that find the solve
+# finished.  48^3, SPE: caps of 6/9/12/16/20/24 gave 1757/1849/1899/1931/
+# 1961/1975 steps/s over steps 6-25 (after 5 warm-up steps, 20.3 PCG
+# iterations per step) and 3320/3373/3353/3331/3339/3338 over steps 41-240
+# (warm-up median 13, 6.5 iterations per step)
+BUDGET_CAP_NODE = 24
 
 
 def log(*a):

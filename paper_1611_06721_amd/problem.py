@@ -109,10 +109,10 @@ class Problem:
             self.lib.ec_destroy(h)
         self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the HIP runtime (or a profiler wrapped around
         # it) may already be gone: leave the process teardown to free it
-        if not sys.is_finalizing():
+        if not _finalizing():
             self.close()
 
     def zeros(self):
@@ -284,8 +284,8 @@ class Graph:
             self.lib.ec_graph_destroy(self.g)
         self.g = None
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():
             self.close()
 
 
@@ -354,7 +354,7 @@ class Batch:
             self.lib.ec_batch_destroy(self.b)
         self.b = None
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():
             self.close()
 
