@@ -280,6 +280,45 @@ int32_t ec_counters_reset(ec_handle h);
 int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, double rtol,
                double *lambda_max);
 
+/* Device-side estimate of the explicit Euler bound (eq. 8; the paper finds
+ * lambda_max by the power method) at state A (device padded; its conducting
+ * part sets the reluctivity): `iters` power iterations on
+ *   jacobian = 1: M_c^{-1} (J_N(A) - S), J_N the derivative of
+ *                 N(a) = [C^T M_nu(a) C a]_C (the step linearised at A);
+ *   jacobian = 0: M_c^{-1} (K_c(nu(A)) - S) = M_c^{-1} K_S(A) of eq. (8),
+ * S = K_cn K_n^+ K_cn^T, run as the transpose (X^T - S) M_c^{-1} (same
+ * eigenvalues) with Euclidean normalisation on the device: no host copies
+ * or synchronisation beyond those of eager PCG solves.  Each iteration is
+ * one K_n^+ solve (rtol) of the EC_SEQ_USER sequence, whose history the call
+ * resets, started as `method` says (EC_SV_ZERO, EC_SV_PREV or EC_SV_SPE over
+ * `window` columns: consecutive right-hand sides converge, so SPE starts
+ * shorten the solves).  *lambda_dev (device double) receives ||B v|| for the
+ * unit iterate v after each iteration (|lambda|_max in the limit);
+ * rec_dev (device, 2 * iters doubles, may be NULL) the pairs
+ * (||B v||, v^T B v) per iteration.  Asynchronous; not capturable
+ * (EC_ERR_STATE under capture).  EC_ERR_ARG for bad arguments or a problem
+ * without conducting edges. */
+int32_t ec_cfl_estimate(ec_handle h, const double *A, int32_t iters, double rtol, int32_t method,
+                        int32_t window, int32_t jacobian, double *lambda_dev, double *rec_dev);
+
+/* Adaptive steps: with lambda_dev (device double, e.g. the output of
+ * ec_cfl_estimate, re-estimated whenever the caller likes) every later step
+ * of the handle (eager, captured or batched) reads it on the device and
+ * takes dt_m = dt 2^-k with the smallest k >= 0 such that
+ * dt_m * lambda <= 2 * safety, dt being the step call's argument (the
+ * largest step); a non-positive or non-finite lambda leaves dt_m = dt.  The
+ * source time advances as t_m = t_{m-1} + dt_m (ramp sources stay indexed by
+ * m), and the EC_ERR_CFL check of ec_cfl does not apply.  lambda_dev = NULL
+ * returns to fixed steps (t_m = m dt).  0 < safety <= 1 (EC_ERR_ARG
+ * otherwise).  The handle keeps the pointer: it must stay valid while steps
+ * run.  The adjoint calls do not support adaptive steps. */
+int32_t ec_set_adaptive_dt(ec_handle h, const double *lambda_dev, double safety);
+
+/* Step index m, source time t_m and step dt_m of the last step (host
+ * outputs, each may be NULL).  t restarts at 0 with ec_set_state.
+ * Synchronises. */
+int32_t ec_clock(ec_handle h, int64_t *m, double *t, double *dt);
+
 /* Replace material mat_id (1..n_mats) of the handle: conductivity and
  * Brauer coefficients (eq. 1).  M_sigma of the conducting edges is rebuilt;
  * the conducting edge set, K_n and the start-vector histories stay valid

@@ -96,6 +96,11 @@ SIGNATURES = {
     "ec_set_step": (C.c_int32, [_H, C.c_int64]),
     "ec_cfl": (C.c_int32, [_H, _P, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "ec_set_material": (C.c_int32, [_H, C.c_int32, C.POINTER(Material)]),
+    "ec_cfl_estimate": (C.c_int32, [_H, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                    C.c_int32, _P, _P]),
+    "ec_set_adaptive_dt": (C.c_int32, [_H, _P, C.c_double]),
+    "ec_clock": (C.c_int32, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                             C.POINTER(C.c_double)]),
     "ec_adjoint_sizes": (C.c_int32, [_H, C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
     "ec_adjoint_forward": (C.c_int32, [_H, C.c_int64, C.c_double, C.c_int32, C.POINTER(StepOpts),
                                        _P, C.c_int64, _P, _P]),

@@ -22,7 +22,6 @@
 
 namespace ec {
 
-constexpr int kCellRec = 5;   // per cell: nu, gamma, B_x, B_y, B_z
 
 // flux of x through the face with normal n anchored at node (i, j, k)
 // (right-handed circulation, same orientation as the curl-curl stencil)
@@ -79,9 +78,14 @@ __global__ void __launch_bounds__(256)
             const double fa[6] = {face_flux(g, a, 0, i, j, k), face_flux(g, a, 0, i + 1, j, k),
                                   face_flux(g, a, 1, i, j, k), face_flux(g, a, 1, i, j + 1, k),
                                   face_flux(g, a, 2, i, j, k), face_flux(g, a, 2, i, j, k + 1)};
-            const double fw[6] = {face_flux(g, w, 0, i, j, k), face_flux(g, w, 0, i + 1, j, k),
-                                  face_flux(g, w, 1, i, j, k), face_flux(g, w, 1, i, j + 1, k),
-                                  face_flux(g, w, 2, i, j, k), face_flux(g, w, 2, i, j, k + 1)};
+            // no direction (w = nullptr): gamma = 0, the records of the
+            // secant operator K_c(nu(a))
+            double fw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (w) {
+                fw[0] = face_flux(g, w, 0, i, j, k); fw[1] = face_flux(g, w, 0, i + 1, j, k);
+                fw[2] = face_flux(g, w, 1, i, j, k); fw[3] = face_flux(g, w, 1, i, j + 1, k);
+                fw[4] = face_flux(g, w, 2, i, j, k); fw[5] = face_flux(g, w, 2, i, j, k + 1);
+            }
             const double B[3] = {0.5 * (fa[0] + fa[1]) / face_area(g, 0),
                                  0.5 * (fa[2] + fa[3]) / face_area(g, 1),
                                  0.5 * (fa[4] + fa[5]) / face_area(g, 2)};
@@ -266,6 +270,70 @@ void adj_accum(const double *part, int nb, double coef, double *acc, hipStream_t
 void adj_zero(double *acc, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_adj_zero, dim3(1), dim3(64), 0, st, acc, n);
+}
+
+
+// ------------------------------------------------- stability estimate (eq. 8)
+// Power method on B = (X^T - S) M_c^{-1}, the transpose of M_c^{-1} (X - S)
+// (X = J_N(a) or K_c(nu(a)); same eigenvalues), on compact conducting-edge
+// vectors: one block, fixed-order sums (deterministic).
+
+// counter-based start vector: splitmix64 of the edge's list position, uniform
+// in [-1/2, 1/2), normalised to unit Euclidean length
+__device__ __forceinline__ double unit_hash(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+__global__ void __launch_bounds__(1024) k_power_init(int nc, double *v)
+{
+    double s[1] = {0.0};
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+        const double x = unit_hash((uint64_t)e);
+        v[e] = x;
+        s[0] += x * x;
+    }
+    block_sum<1>(s);
+    const double inv = s[0] > 0.0 ? 1.0 / sqrt(s[0]) : 0.0;
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) v[e] *= inv;
+}
+
+// y = B v for the unit iterate v: lambda = ||y|| (stored), v <- y / ||y||;
+// rec (may be null) receives {lambda, v^T y}
+__global__ void __launch_bounds__(1024)
+    k_power_norm(int nc, const double *__restrict__ y, double *v, double *lam, double *rec)
+{
+    double s[2] = {0.0, 0.0};
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+        const double ye = y[e];
+        s[0] += ye * ye;
+        s[1] += v[e] * ye;
+    }
+    block_sum<2>(s);
+    const double l = sqrt(s[0]);
+    const double inv = l > 0.0 ? 1.0 / l : 0.0;
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) v[e] = y[e] * inv;
+    if (threadIdx.x == 0) {
+        *lam = l;
+        if (rec) {
+            rec[0] = l;
+            rec[1] = s[1];
+        }
+    }
+}
+
+void power_init(int nc, double *v, hipStream_t st)
+{
+    if (nc > 0) hipLaunchKernelGGL(k_power_init, dim3(1), dim3(1024), 0, st, nc, v);
+}
+
+void power_norm(int nc, const double *y, double *v, double *lam, double *rec, hipStream_t st)
+{
+    if (nc > 0) hipLaunchKernelGGL(k_power_norm, dim3(1), dim3(1024), 0, st, nc, y, v, lam, rec);
 }
 
 }  // namespace ec

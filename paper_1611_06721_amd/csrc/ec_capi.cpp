@@ -65,6 +65,10 @@ struct ec_problem {
     // largest eigenvalue of M_c^{-1} K_S from the last ec_cfl (0: none since
     // bind or the last material change); steps with dt above 2 / cfl_lam fail
     double cfl_lam = 0.0;
+    // adaptive steps (ec_set_adaptive_dt): device estimate of |lambda|_max and
+    // the safety factor of the halving rule; null: fixed steps
+    const double *adapt_lam = nullptr;
+    double adapt_safety = 0.5;
     double dep_tol = kDepTol;    // SPE linear-independence threshold (relative)
     double seq_eta[EC_NSEQ] = {};  // grad-div weight the stored SPE matrix was built with
     // per-sequence iteration budget of the solves being captured (0 = maxit)
@@ -80,6 +84,9 @@ struct ec_problem {
     uint8_t *cls_d = nullptr, *cmat_d = nullptr;
     int *cslot_d = nullptr;
     double *minv_d = nullptr, *cvec_d = nullptr;
+    // stability estimate: the power iterate (compact), the cell records of
+    // the operator and the cell pass's partials
+    double *cvec2_d = nullptr, *cellv_d = nullptr, *part_cell = nullptr;
     Mats *mats_d = nullptr;
     SeqDev *seq_d = nullptr;
     Ctrl *ctrl_d = nullptr;
@@ -377,6 +384,9 @@ static int64_t layout(ec_problem *h, int cap, char *base)
     h->cslot_d = (int *)take((int64_t)std::max(h->nc, 1) * 4);
     h->minv_d = (double *)take((int64_t)std::max(h->nc, 1) * 8);
     h->cvec_d = (double *)take((int64_t)std::max(h->nc, 1) * 8);
+    h->cvec2_d = (double *)take((int64_t)std::max(h->nc, 1) * 8);
+    h->cellv_d = (double *)take(std::max<int64_t>(h->ncell, 1) * kCellRec * 8);
+    h->part_cell = (double *)take((h->ncell + 255) / 256 * 8 + 8);
     h->mats_d = (Mats *)take(sizeof(Mats));
     h->seq_d = (SeqDev *)take(sizeof(SeqDev) * EC_NSEQ);
     h->ctrl_d = (Ctrl *)take(sizeof(Ctrl));
@@ -1372,7 +1382,8 @@ static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const e
         seq_push_n(h, 1, &seq, meth, &x, sd, 1);
         HIP_TRY(h, hipEventRecord(h->sev[1], sd));
     }
-    step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st);
+    step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st, h->adapt_lam,
+               h->adapt_safety);
     int32_t rc = do_solve(h, EC_SEQ_SRC, meth, o->window, o->pod_kmax, o->pod_eps, h->xs_d,
                           &h->ctrl_d->scale, h->sj, &o->solve, info, false);
     if (rc) return rc;
@@ -1411,7 +1422,7 @@ static int32_t check_step_args(ec_problem *h, double dt, const double *A, const 
 {
     if (!aligned(A) || !o) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(h, EC_ERR_ARG, "dt must be positive");
-    if (h->cfl_lam > 0.0 && dt * h->cfl_lam > 2.0)
+    if (!h->adapt_lam && h->cfl_lam > 0.0 && dt * h->cfl_lam > 2.0)
         return fail(h, EC_ERR_CFL,
                     "dt %.6g above the explicit Euler bound 2/lambda_max = %.6g of the last "
                     "ec_cfl (eq. 8)", dt, 2.0 / h->cfl_lam);
@@ -1470,6 +1481,7 @@ static int32_t set_state_impl(ec_problem *h, const double *A, const ec_solve_opt
                           nullptr, false);
     if (rc) return rc;
     fill(h->sj, 0.0, h->npad, st);
+    fill(&h->ctrl_d->t, 0.0, 1, st);     // the clock of adaptive steps starts at 0
     for (int s = 0; s < EC_NSEQ; ++s) seq_reset(h->seq_d + s, st);
     HIP_TRY(h, hipStreamSynchronize(st));
     return launch_check(h, "set state");
@@ -1570,6 +1582,89 @@ extern "C" int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, dou
     *lambda_max = lam;
     if (std::isfinite(lam) && lam > 0.0) h->cfl_lam = lam;
     return launch_check(h, "cfl");
+}
+
+// ------------------------------------------------- stability estimate
+// Power method for the explicit Euler bound (eq. 8 and the power method named
+// after it) with the reluctivity at state A: B = (X^T - S) M_c^{-1},
+// X = J_N(A) (jacobian) or K_c(nu(A)); B is the transpose of
+// M_c^{-1} (X - S), so it has its eigenvalues.  Per iteration, with the unit
+// iterate v (compact): w = M_c^{-1} v on C; cell records of X at A (and w
+// for J_N); s = K_n^+ K_cn^T w, one solve of the EC_SEQ_USER sequence started
+// as `method` says (the right-hand sides of consecutive iterations converge:
+// SPE extrapolates them); y = [C^T (M_nu C u + q)]_C with u = w on C and -s
+// on N, i.e. X^T w - S w; lambda = ||y||, v <- y / lambda on the device.
+// Scratch: the second push set (w_b, t2_b..t4_b), free outside captures.
+extern "C" int32_t ec_cfl_estimate(ec_handle h, const double *A, int32_t iters, double rtol,
+                                   int32_t method, int32_t window, int32_t jacobian,
+                                   double *lambda_dev, double *rec_dev)
+{
+    NEED_BOUND(h);
+    flush_pending(h);
+    if (!aligned(A) || !lambda_dev || iters < 1 || !(rtol > 0))
+        return fail(h, EC_ERR_ARG, "need aligned A, lambda_dev, iters >= 1, rtol > 0");
+    if (method != EC_SV_ZERO && method != EC_SV_PREV && method != EC_SV_SPE)
+        return fail(h, EC_ERR_ARG, "inner solves start from zero, the previous or an SPE vector");
+    if (method == EC_SV_SPE && (window < 1 || window > h->cap))
+        return fail(h, EC_ERR_ARG, "window must be 1..%d", h->cap);
+    if (h->nc == 0) return fail(h, EC_ERR_ARG, "no conducting edges");
+    if (capturing(h)) return fail(h, EC_ERR_STATE, "the estimate is not captured");
+    hipStream_t st = h->st;
+    const int nc = h->nc;
+    double *wpad = h->t2_b, *upad = h->t3_b, *bpad = h->t4_b, *spad = h->w_b;
+    adj_cell_init(h->cellv_d, h->ncell, h->mats.nu0, st);
+    fill(wpad, 0.0, h->npad, st);
+    fill(bpad, 0.0, h->npad, st);
+    fill(spad, 0.0, h->npad, st);
+    power_init(nc, h->cvec2_d, st);
+    const int seq = EC_SEQ_USER;
+    const int win = method == EC_SV_SPE ? window : 1;
+    if (method == EC_SV_SPE) {
+        seq_ensure(h, seq, method, win, win, 1e-4);
+        seq_eta_ensure(h, seq, method, spe_eta(h, EC_PREC_FP64));
+    }
+    seq_reset(h->seq_d + seq, st);
+    const ec_solve_opts o{rtol, 1000000, EC_PREC_FP64, 0.0, 0, 0};
+    for (int it = 0; it < iters; ++it) {
+        adj_w(h->cslot_d, nc, h->cvec2_d, h->minv_d, wpad, st);
+        if (jacobian || it == 0)
+            adj_cell(h->g, h->mats_d, h->cmat_d, A, jacobian ? wpad : nullptr, h->cellv_d, 1,
+                     h->bblo, h->bbhi, h->part_cell, st);
+        if (h->has_cond) spmv(h->g, wpad, bpad, h->band_lo, h->band_hi, st);
+        int32_t rc = do_solve(h, seq, method, win, win, 1e-4, bpad, nullptr, spad, &o, nullptr,
+                              true);
+        if (rc) return rc;
+        negate(spad, upad, h->npad, st);
+        adj_w(h->cslot_d, nc, h->cvec2_d, h->minv_d, upad, st);
+        adj_edge(h->g, h->cslot_d, nc, h->cellv_d, upad, h->cvec_d, st);
+        power_norm(nc, h->cvec_d, h->cvec2_d, lambda_dev, rec_dev ? rec_dev + 2 * it : nullptr,
+                   st);
+    }
+    return launch_check(h, "stability estimate");
+}
+
+extern "C" int32_t ec_set_adaptive_dt(ec_handle h, const double *lambda_dev, double safety)
+{
+    NEED_BOUND(h);
+    flush_pending(h);
+    if (lambda_dev && (!(safety > 0.0) || !(safety <= 1.0) ||
+                       ((uintptr_t)lambda_dev % 8) != 0))
+        return fail(h, EC_ERR_ARG, "need 0 < safety <= 1 and an 8-byte aligned device scalar");
+    h->adapt_lam = lambda_dev;
+    h->adapt_safety = lambda_dev ? safety : 0.5;
+    return EC_OK;
+}
+
+extern "C" int32_t ec_clock(ec_handle h, int64_t *m, double *t, double *dt)
+{
+    NEED_BOUND(h);
+    Ctrl c{};
+    HIP_TRY(h, hipMemcpyAsync(&c, h->ctrl_d, sizeof c, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    if (m) *m = c.step;
+    if (t) *t = c.t;
+    if (dt) *dt = c.dt;
+    return EC_OK;
 }
 
 // ------------------------------------------------------------ graphs
@@ -1744,6 +1839,8 @@ static int32_t adj_args(ec_problem *h, int64_t n_steps, double dt, int32_t every
     int32_t rc = check_step_args(h, dt, A ? A : h->ac, opts);
     if (rc) return rc;
     if (!h->has_cond) return fail(h, EC_ERR_ARG, "the adjoint needs a conductor");
+    if (h->adapt_lam)
+        return fail(h, EC_ERR_STATE, "the adjoint runs fixed steps: ec_set_adaptive_dt(h, NULL, 0)");
     if (n_steps < 1 || every < 1) return fail(h, EC_ERR_ARG, "need n_steps >= 1, every >= 1");
     if (!ws || ((uintptr_t)ws % kAlign) != 0)
         return fail(h, EC_ERR_ARG, "adjoint workspace must be 256-byte aligned");
@@ -2028,7 +2125,8 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
         b->npad_max = 0;
         for (size_t i = 0; i < ni; ++i) {
             ec_problem *h = b->inst[i];
-            stp[i] = StepArgs{h->ctrl_d, h->wf, h->amp, h->freq, h->tau, h->ramp, dt[i]};
+            stp[i] = StepArgs{h->ctrl_d, h->wf,  h->amp,        h->freq,         h->tau,
+                              h->ramp,   dt[i], h->adapt_lam, h->adapt_safety};
             UpdArgs &u = upd[i];
             u = UpdArgs{};
             u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d;

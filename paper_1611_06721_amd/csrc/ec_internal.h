@@ -101,6 +101,7 @@ struct Ctrl {
     int refine_zero;         // the right-hand side was zero
     double refine_rr, refine_bb;
     double refine_tol;       // relative tolerance of the next inner FP32 solve
+    double t;                // time t_m of the current step (adaptive steps accumulate it)
 };
 
 // ----------------------------------------------------------------- launchers
@@ -330,8 +331,12 @@ void update_c_tab(const UpdArgs *tab, int n, int nc_max, hipStream_t st);
 
 void finish_state(const Geo &g, double *A, const double *ac, const double *sj,
                   const double *sc, Ctrl *ctrl, int bump, hipStream_t st);
+// lam (device scalar, may be null): adaptive step dt 2^-k, the smallest
+// k >= 0 with dt_m lam <= 2 safety, and t_m = t_{m-1} + dt_m; otherwise
+// t_m = m dt
 void step_begin(Ctrl *ctrl, int64_t m, int wf, double amp, double freq, double tau,
-                int64_t ramp, double dt, hipStream_t st);
+                int64_t ramp, double dt, hipStream_t st, const double *lam = nullptr,
+                double safety = 0.5);
 // the same for the n instances of a batch, one launch each
 struct FinArgs {
     int64_t n;
@@ -346,6 +351,8 @@ struct StepArgs {
     double amp, freq, tau;
     int64_t ramp;
     double dt;
+    const double *lam;       // adaptive step (see step_begin), may be null
+    double safety;
 };
 void step_begin_tab(const StepArgs *tab, int n, int64_t m, hipStream_t st);
 void fill(double *y, double v, int64_t n, hipStream_t st);
@@ -368,6 +375,14 @@ void seq_config(SeqDev *seq, int method, int cap, int kmax, double eps, double h
 // an explicit history push (not after a solve): the next push is not skipped
 void seq_push_on(SeqDev *seq, hipStream_t st);
 void negate(const double *x, double *y, int64_t n, hipStream_t st);
+
+constexpr int kCellRec = 5;   // adjoint / stability cell records: nu, gamma, B_x, B_y, B_z
+
+// power method of the stability estimate (eq. 8) on compact conducting-edge
+// vectors (one block each): a unit start vector, and the normalisation of
+// y = B v (lambda = ||y|| into *lam, v <- y / lambda, rec = {lambda, v^T y})
+void power_init(int nc, double *v, hipStream_t st);
+void power_norm(int nc, const double *y, double *v, double *lam, double *rec, hipStream_t st);
 
 // discrete adjoint of the time loop (ec_adjoint.hip); the *part launchers
 // return the number of block partials they wrote

@@ -175,12 +175,26 @@ void finish_state_tab(const FinArgs *tab, int n, int64_t npad_max, hipStream_t s
 
 // i_S(t_m) of the source waveforms (DC, sine, linear ramp, 1 - exp(-t/tau)).
 __device__ __forceinline__ void step_begin_body(Ctrl *ctrl, int64_t m_arg, int wf, double amp,
-                                                double freq, double tau, int64_t ramp, double dt)
+                                                double freq, double tau, int64_t ramp, double dt,
+                                                const double *lam, double safety)
 {
     const int64_t m = m_arg >= 0 ? m_arg : ctrl->step + 1;
     ctrl->step = m;
-    ctrl->dt = dt;
-    const double t = (double)m * dt;
+    double t;
+    if (lam) {
+        // adaptive step: halve dt until dt lambda <= 2 safety (eq. 8 with a
+        // margin); a non-positive or non-finite estimate leaves dt as given
+        const double l = *lam;
+        double dm = dt;
+        if (l > 0.0 && l < 1e300)
+            for (int q = 0; q < 64 && dm * l > 2.0 * safety; ++q) dm *= 0.5;
+        ctrl->dt = dm;
+        t = ctrl->t + dm;
+    } else {
+        ctrl->dt = dt;
+        t = (double)m * dt;
+    }
+    ctrl->t = t;
     double s = 0.0;
     switch (wf) {
     case EC_WF_DC: s = amp; break;
@@ -193,16 +207,17 @@ __device__ __forceinline__ void step_begin_body(Ctrl *ctrl, int64_t m_arg, int w
 }
 
 __global__ void k_step_begin(Ctrl *ctrl, int64_t m_arg, int wf, double amp, double freq,
-                             double tau, int64_t ramp, double dt)
+                             double tau, int64_t ramp, double dt, const double *lam,
+                             double safety)
 {
-    step_begin_body(ctrl, m_arg, wf, amp, freq, tau, ramp, dt);
+    step_begin_body(ctrl, m_arg, wf, amp, freq, tau, ramp, dt, lam, safety);
 }
 
 // one instance of a batch per block row
 __global__ void k_step_begin_tab(const StepArgs *tab, int64_t m_arg)
 {
     const StepArgs &s = tab[blockIdx.y];
-    step_begin_body(s.ctrl, m_arg, s.wf, s.amp, s.freq, s.tau, s.ramp, s.dt);
+    step_begin_body(s.ctrl, m_arg, s.wf, s.amp, s.freq, s.tau, s.ramp, s.dt, s.lam, s.safety);
 }
 
 void step_begin_tab(const StepArgs *tab, int n, int64_t m, hipStream_t st)
@@ -211,10 +226,10 @@ void step_begin_tab(const StepArgs *tab, int n, int64_t m, hipStream_t st)
 }
 
 void step_begin(Ctrl *ctrl, int64_t m, int wf, double amp, double freq, double tau, int64_t ramp,
-                double dt, hipStream_t st)
+                double dt, hipStream_t st, const double *lam, double safety)
 {
     hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, st, ctrl, m, wf, amp, freq, tau, ramp,
-                       dt);
+                       dt, lam, safety);
 }
 
 __global__ void k_fill(double *y, double v, int64_t n)

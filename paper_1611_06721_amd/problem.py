@@ -224,6 +224,31 @@ class Problem:
             self._chk(self.lib.ec_cfl(self.h, _ptr(A), iters, rtol, C.byref(lam)))
         return lam.value
 
+    def cfl_estimate(self, A=None, iters=30, rtol=1e-10, method=L.SV_SPE, window=8,
+                     jacobian=True, lam=None, rec=None):
+        """Device power-method estimate of |lambda|_max (eq. 8) at state A into
+        the device scalar `lam` (a new float64 tensor if None), asynchronously."""
+        A = self.zeros() if A is None else A
+        lam = torch.zeros(1, dtype=torch.float64, device=self.device) if lam is None else lam
+        with self._on_stream():
+            self._chk(self.lib.ec_cfl_estimate(self.h, _ptr(A), int(iters), float(rtol),
+                                               int(method), int(window), 1 if jacobian else 0,
+                                               _ptr(lam), _ptr(rec)))
+        return lam
+
+    def set_adaptive_dt(self, lam, safety=0.5):
+        """Steps read the device estimate `lam` and halve dt to meet it (None:
+        fixed steps).  The tensor must outlive the steps that use it."""
+        self._adapt_lam = lam
+        with self._on_stream():
+            self._chk(self.lib.ec_set_adaptive_dt(self.h, _ptr(lam), float(safety)))
+
+    def clock(self):
+        m, t, dt = C.c_int64(), C.c_double(), C.c_double()
+        with self._on_stream():
+            self._chk(self.lib.ec_clock(self.h, C.byref(m), C.byref(t), C.byref(dt)))
+        return m.value, t.value, dt.value
+
     def set_material(self, mat_id, sigma, k1, k2, k3):
         m = L.Material(float(sigma), float(k1), float(k2), float(k3))
         with self._on_stream():
