@@ -381,10 +381,15 @@ int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt, int32_t che
  * counters (ec_counters) record the solves.  Eager calls synchronise once
  * per handful of iterations to stop when every solve has finished.
  * ec_batch_graph_capture: one step of every instance as one HIP graph
- * (device step counters; opts->graph_iters = batched iterations per solve,
- * 0 = solve.maxit up to 4096; a solve that needs more reports
- * EC_ERR_NOT_CONVERGED in its instance's worst status); launch with
- * ec_graph_launch.
+ * (device step counters; opts->graph_iters = batched iteration launches per
+ * solve, 0 = solve.maxit up to 4096).  With a budget B below solve.maxit the
+ * graph issues B - 1 batched iteration launches and then one persistent
+ * launch that runs the B-th and every further iteration of each unfinished
+ * instance over the same block map and iteration bodies (a grid barrier
+ * between iterations) until all have finished or reached solve.maxit: the
+ * results are those of eager batch steps, bitwise, whatever the budget, and
+ * a budget of 1 makes each batched PCG solve one persistent launch after
+ * its init.  Launch with ec_graph_launch.
  * ec_batch_set_tiles / ec_batch_autotune: the tiles of 256 nodes each block
  * of a batched iteration sweeps (1..64).  The autotuner times 1, 2, 4 and 8
  * on the batch itself, each as one iteration launch with every solve active

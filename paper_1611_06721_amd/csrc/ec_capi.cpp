@@ -2025,6 +2025,7 @@ struct ec_batch_s {
     int total_blocks = 0, max_blocks = 0;
     int tiles_per_block = 1;
     bool one_tile = true;                          // every instance: one tile per block
+    int tail_blocks = 0;                           // grid of the batched tail (0: none)
 };
 
 static int64_t batch_layout(const std::vector<ec_problem *> &hs, char *base, ec_batch_s *b)
@@ -2255,9 +2256,20 @@ static int32_t batch_solve(ec_batch_s *b, int s, const ec_step_opts *o)
     if (capturing(h0)) {
         int budget = std::min(maxit, kGraphMaxIters);
         if (o->graph_iters[s] > 0) budget = std::min(budget, o->graph_iters[s]);
-        for (int it = 0; it < budget; ++it)
+        // a budget below maxit: the last budgeted iteration and any further
+        // ones of every instance run in one persistent launch over the block
+        // map (same iteration bodies, so the same results as eager steps)
+        const bool tail = budget < maxit && b->tail_blocks > 0;
+        const int kernels = tail ? budget - 1 : budget;
+        for (int it = 0; it < kernels; ++it)
             cg_iter_batch(b->tab_d[s], b->inst_d, b->off_d, b->total_blocks, it, b->one_tile,
                           b->st);
+        if (tail) {
+            hipError_t e = cg_tail_batch(b->tab_d[s], n, b->inst_d, b->off_d, b->total_blocks,
+                                         kernels, b->tail_blocks, b->one_tile, b->st);
+            if (e != hipSuccess)
+                return fail(h0, EC_ERR_HIP, "batched tail launch: %s", hipGetErrorString(e));
+        }
         issued = budget;
     } else {
         int chunk = 8;
@@ -2367,6 +2379,7 @@ extern "C" int32_t ec_batch_create(int32_t n, const ec_handle *handles, void *wo
     b->inst = hs;
     b->st = hs[0]->st;
     batch_layout(hs, (char *)workspace, b);
+    b->tail_blocks = cg_tail_batch_blocks();
     rc = batch_apply_tiles(b, 1);
     if (rc) {
         delete b;

@@ -220,6 +220,12 @@ void cg_init_batch(const CgArgs<double> *tab, const int *inst, const int *off, i
                    int mode, hipStream_t st);
 void cg_fin_batch(const CgArgs<double> *tab, int n, int iters, hipStream_t st);
 void batch_done(const CgArgs<double> *tab, int n, int it, int *flag, hipStream_t st);
+// iterations it0.. of every unfinished solve of a batch in one persistent
+// launch over the block map (grid: at most cg_tail_batch_blocks(), all
+// resident; the barrier words are tab[0].bar); 0 blocks: not available
+int cg_tail_batch_blocks();
+hipError_t cg_tail_batch(const CgArgs<double> *tab, int n, const int *inst, const int *off,
+                         int total, int it0, int blocks, bool one_tile, hipStream_t st);
 // blocks of the persistent tail (at most two per CU, all resident at once, a
 // multiple of 8; 0 on failure)
 template <typename T>

@@ -702,20 +702,22 @@ __global__ void __launch_bounds__(256) k_cg_iter(CgArgs<T> a, int it)
 // the single-instance kernel for that case, so each instance's iteration is
 // the same compiled arithmetic as when it is stepped alone; otherwise the
 // general body (one instantiation per path keeps the registers of each).
+// Block vb of the batch's block map in iteration it (the launched batched
+// kernel and the batched tail run this same body, so an instance's
+// iteration is the same compiled arithmetic in both).
 template <bool HOISTED>
-__global__ void __launch_bounds__(256)
-    k_cg_iter_batch(const CgArgs<double> *__restrict__ tab, const int *__restrict__ inst,
-                    const int *__restrict__ off, int it)
+__device__ __forceinline__ void batch_iter_body(const CgArgs<double> *__restrict__ tab,
+                                                const int *__restrict__ inst,
+                                                const int *__restrict__ off, int vb, int it,
+                                                CgCtl &s_c, double &s_beta)
 {
-    const int i = inst[blockIdx.x];
+    const int i = inst[vb];
     const CgArgs<double> &a = tab[i];
-    const int bid = blockIdx.x - off[i];
+    const int bid = vb - off[i];
     if (a.ctl[it & 1].done) {
         if (bid == 0 && threadIdx.x == 0) a.ctl[(it + 1) & 1] = a.ctl[it & 1];
         return;
     }
-    __shared__ CgCtl s_c;
-    __shared__ double s_beta;
     if constexpr (HOISTED) {
         cg_iter_hoisted<double>(a, it, a.blocks, s_c, s_beta, bid);
     } else {
@@ -724,6 +726,16 @@ __global__ void __launch_bounds__(256)
         if (cg_decide<double>(a, it, t, s_c, s_beta, bid)) return;
         cg_update<double>(a, it, s_c, s_beta, bid, a.blocks);
     }
+}
+
+template <bool HOISTED>
+__global__ void __launch_bounds__(256)
+    k_cg_iter_batch(const CgArgs<double> *__restrict__ tab, const int *__restrict__ inst,
+                    const int *__restrict__ off, int it)
+{
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    batch_iter_body<HOISTED>(tab, inst, off, blockIdx.x, it, s_c, s_beta);
 }
 
 // *flag = 1 if every solve of the batch has finished before iteration it
@@ -1085,6 +1097,101 @@ __global__ void __launch_bounds__(256, 2) k_cg_tail(CgArgs<T> a, int it0, unsign
     }
     // the solve's final step (as k_cg_fin) on the record just stored
     if (fin && blockIdx.x == 0) cg_fin_body<T>(a, it0 + 1);
+}
+
+// Finishes the batched solves that the captured iteration launches left
+// unfinished: iterations it0, it0+1, ... of every instance in one persistent
+// launch.  Its blocks sweep the batch's block map (block vb = blockIdx.x +
+// q gridDim.x runs batch_iter_body for vb, the launched kernel's block vb),
+// a grid barrier between iterations; after each barrier every block reads
+// the n records and the sweep ends once all solves are done.  Then block 0
+// puts each instance's final record into both control slots, so that the
+// final step of the budget (k_cg_fin_tab for it0 + 1 iterations) reads it.
+// The barrier words are instance 0's (cleared by its init).
+template <bool HOISTED>
+__global__ void __launch_bounds__(256, 2)
+    k_cg_tail_batch(const CgArgs<double> *__restrict__ tab, int n, const int *__restrict__ inst,
+                    const int *__restrict__ off, int total, int it0)
+{
+    __shared__ CgCtl s_c;
+    __shared__ double s_beta;
+    __shared__ int s_all;
+    unsigned *bar = tab[0].bar;
+    // the usual case: the launched iterations finished every solve
+    if (threadIdx.x == 0) {
+        int all = 1;
+        for (int i = 0; i < n; ++i) all &= tab[i].ctl[it0 & 1].done;
+        s_all = all;
+    }
+    __syncthreads();
+    if (s_all) {
+        if (blockIdx.x == 0)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i].ctl[(it0 + 1) & 1] =
+                tab[i].ctl[it0 & 1];
+        return;
+    }
+    unsigned gen = 0;
+    BarState bs;
+    bool ok = true;
+    int it = it0;
+    for (;; ++it) {
+        for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+            batch_iter_body<HOISTED>(tab, inst, off, vb, it, s_c, s_beta);
+            __syncthreads();     // shared records reused by the next block of the sweep
+        }
+        ok = grid_barrier(bar, ++gen, bs);
+        if (!ok) break;
+        if (threadIdx.x == 0) {
+            int all = 1;
+            for (int i = 0; i < n; ++i) all &= tab[i].ctl[(it + 1) & 1].done;
+            s_all = all;
+        }
+        __syncthreads();
+        if (s_all) break;
+    }
+    // every block has read the records of the last iteration
+    if (ok) ok = grid_barrier(bar, ++gen, bs);
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            CgCtl f = tab[i].ctl[(it + 1) & 1];
+            if (!ok) {
+                f.done = 1;
+                f.status = EC_ERR_HIP;
+            }
+            tab[i].ctl[0] = f;
+            tab[i].ctl[1] = f;
+        }
+    }
+}
+
+int cg_tail_batch_blocks()
+{
+    int dev = 0, cus = 0, p0 = 0, p1 = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, k_cg_tail_batch<false>, kTile, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, k_cg_tail_batch<true>, kTile, 0) !=
+            hipSuccess)
+        return 0;
+    const int per = std::min(p0, p1);
+    if (per < 1) return 0;
+    // at most two blocks per CU, a multiple of 8: all resident at once
+    return std::min((cus * std::min(per, 2)) & ~7, kMaxBlocks);
+}
+
+hipError_t cg_tail_batch(const CgArgs<double> *tab, int n, const int *inst, const int *off,
+                         int total, int it0, int blocks, bool one_tile, hipStream_t st)
+{
+    const int nb = std::min(blocks, ((total + 7) / 8) * 8);
+    if (one_tile)
+        hipLaunchKernelGGL(k_cg_tail_batch<true>, dim3(nb), dim3(kTile), 0, st, tab, n, inst, off,
+                           total, it0);
+    else
+        hipLaunchKernelGGL(k_cg_tail_batch<false>, dim3(nb), dim3(kTile), 0, st, tab, n, inst, off,
+                           total, it0);
+    return hipGetLastError();
 }
 
 // After `iters` iteration kernels: final decision on the last iterate, the

@@ -106,6 +106,48 @@ def test_batch_graph_equals_eager(ec, oracle_mod):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("tiles", [1, 4])
+def test_batch_graph_starved_budget_equals_eager(ec, oracle_mod, tiles):
+    """Captured batch steps whose solves get one or two iteration launches:
+    the persistent batched tail runs every further iteration of every
+    instance, and the trajectories are the eager ones bit for bit (one tile
+    per block, and several tiles per block)."""
+    import torch
+    wls = instances()
+    dts = [0.5 * 2 / oracle_mod.Problem(w).power(iters=40) for w in wls]
+    opts = ec.step_opts(ec.SV_SPE, window=8, rtol=1e-10)
+    runs = []
+    for budget in (None, (1, 2), (2, 1)):
+        s = torch.cuda.Stream()
+        probs, B = make_batch(ec, wls, s)
+        B.set_tiles(tiles)
+        As = [p.zeros() for p in probs]
+        for p, A in zip(probs, As):
+            p.set_state(A, rtol=1e-10)
+        B.run(0, 6, dts, As, opts)
+        for p in probs:
+            p.counters_reset()
+        if budget is None:
+            B.run(-1, 10, dts, As, opts)
+        else:
+            g = B.graph_capture(dts, As, ec.step_opts(ec.SV_SPE, window=8, rtol=1e-10,
+                                                      graph_iters=budget))
+            for _ in range(10):
+                g.launch()
+            g.close()
+        cs = [p.counters() for p in probs]
+        assert all(c["worst_status"] == 0 and c["steps"] == 10 for c in cs)
+        runs.append(([A.cpu().numpy() for A in As],
+                     [(c["iters_src"], c["iters_cpl"]) for c in cs]))
+        B.close()
+        for p in probs:
+            p.close()
+    for r in runs[1:]:
+        assert r[1] == runs[0][1]
+        for a, b in zip(r[0], runs[0][0]):
+            assert np.array_equal(a, b)
+
+
 def test_batch_autotune_cache(ec, oracle_mod, tmp_path):
     import torch
     wls = instances(count=3)
