@@ -242,8 +242,10 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
     Brauer coefficients within 10 %), each at half its own stability bound,
     SPE m = 8.  After `warmup` eager batched steps, `steps` replays of one
     graph holding every instance's step (batched PCG launches, autotuned
-    grids) are timed, then the same steps as 64 per-instance graphs launched
-    one after the other."""
+    grids, the persistent batched tail past the budget) are timed; then with
+    every batched PCG solve as one persistent launch (budget 1); then the
+    same steps as 64 per-instance graphs launched one after the other."""
+    import numpy as np
     import synth
     wls = synth.batch_workloads(count)
     s = torch.cuda.Stream()
@@ -257,26 +259,29 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
     out = {"workload": f"{count} instances, N in [16, 64], {steps} steps, SPE m=8, rtol {rtol:g}",
            "edges_total": int(sum(p.n_pad for p in probs)),
            "autotuned_tiles_per_block": tiles, "batched_iteration_us": round(tuned_us, 2)}
-    for mode in ("batched_graph", "per_instance_graphs"):
+    for mode in ("batched_graph", "batched_persistent", "per_instance_graphs"):
         As = [p.zeros() for p in probs]
         for p, A in zip(probs, As):
             p.set_state(A, rtol=rtol)
         B.run(0, warmup, dts, As, opts)
-        # iteration budget per solve from the last warm-up steps
-        mx = [0, 0]
+        # iteration budget per solve: the median over the instances of the
+        # largest count of the last warm-up steps; solves that need more
+        # continue in the persistent batched tail
+        mx = np.zeros((len(probs), 2), dtype=np.int64)
         for _ in range(6):
             for p in probs:
                 p.counters_reset()
             B.step(dts, As, opts)
-            for p in probs:
+            for i, p in enumerate(probs):
                 c = p.counters()
-                mx[0] = max(mx[0], c["iters_src"])
-                mx[1] = max(mx[1], c["iters_cpl"])
-        budgets = [int(1.5 * mx[0]) + 4, int(1.5 * mx[1]) + 8]
+                mx[i] = np.maximum(mx[i], [c["iters_src"], c["iters_cpl"]])
+        budgets = [max(2, int(np.median(mx[:, q]))) for q in (0, 1)]
+        if mode == "batched_persistent":
+            budgets = [1, 1]         # every batched PCG solve: one persistent launch
         gopts = ec.step_opts(ec.SV_SPE, window=8, rtol=rtol, graph_iters=tuple(budgets))
         for p in probs:
             p.counters_reset()
-        if mode == "batched_graph":
+        if mode != "per_instance_graphs":
             graphs = [B.graph_capture(dts, As, gopts)]
         else:
             # each problem alone on its own default PCG grid (the batch had
@@ -312,6 +317,7 @@ def batch_c4(ec, torch, steps=300, warmup=20, count=64, rtol=1e-8):
         log(f"[bench] batch {mode}: {out[mode]['instance_steps_per_s']} instance-steps/s")
     out["speedup_batched"] = round(out["batched_graph"]["instance_steps_per_s"] /
                                    out["per_instance_graphs"]["instance_steps_per_s"], 3)
+    out["tail_blocks"] = "persistent batched tail: at most 2 blocks per CU, all resident"
     B.close()
     for p in probs:
         p.close()
