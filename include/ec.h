@@ -61,6 +61,7 @@ enum { EC_SEQ_SRC = 0, EC_SEQ_CPL = 1, EC_SEQ_ADJ = 2, EC_SEQ_USER = 3, EC_NSEQ 
 enum { EC_SV_ZERO = 0, EC_SV_PREV = 1, EC_SV_SPE = 2, EC_SV_POD = 3 };
 enum { EC_PREC_FP64 = 0, EC_PREC_FP32_REFINED = 1 };
 enum { EC_OP_KN = 0, EC_OP_KCN_T = 1, EC_OP_KC_KCN = 2 };
+enum { EC_MASS_LUMPED = 0, EC_MASS_CONSISTENT = 1 };
 
 #define EC_MAX_WINDOW 20
 
@@ -318,6 +319,35 @@ int32_t ec_set_adaptive_dt(ec_handle h, const double *lambda_dev, double safety)
  * outputs, each may be NULL).  t restarts at 0 with ec_set_state.
  * Synchronises. */
 int32_t ec_clock(ec_handle h, int64_t *m, double *t, double *dt);
+
+/* Conductivity matrix M_c of the step (eq. 6).  EC_MASS_LUMPED (default):
+ * the diagonal FIT matrix, M_c^{-1} an edge-wise scale.  EC_MASS_CONSISTENT:
+ * the mass matrix of the lowest-order edge elements on the conducting cells
+ * (per cell and direction sigma h_a1 h_a2 / h_c times 1/9, 1/18 or 1/36 for
+ * an edge with itself, a side apart or diagonally across the transverse
+ * face; its row sums are the lumped matrix), non-diagonal: every step then
+ * solves M_c y = g for its update (the last paragraph of Sec. III names
+ * M_c^{-1} as a further right-hand-side sequence), by Jacobi-PCG (same
+ * single-reduction form as the K_n solves) to rtol, at most maxit
+ * iterations (a captured step issues maxit iteration kernels), started
+ * from zero (EC_SV_ZERO) or from the SPE projection with M_c over the last
+ * `window` solutions of that sequence (EC_SV_SPE, eq. 10 with M_c in place
+ * of K_n).  Resets that history.  Batch steps, the adjoint and the CFL
+ * estimates (ec_cfl, ec_cfl_estimate) use the lumped matrix (batches and the
+ * adjoint refuse a consistent one with EC_ERR_STATE).  EC_ERR_ARG for bad
+ * values.
+ * ec_mass_apply: y = M_c x on the conducting edges (device padded arrays;
+ * y's other entries are left as they are).
+ * ec_mass_solve: M_c y = g (device padded, conducting entries) with the
+ * configured start and tolerance, pushing y into the sequence's history;
+ * dev_info (device, may be NULL) receives the record.
+ * ec_mass_counters: solves with the consistent M_c and their PCG
+ * iterations since bind or ec_counters_reset (synchronises). */
+int32_t ec_set_mass(ec_handle h, int32_t kind, int32_t method, int32_t window, double rtol,
+                    int32_t maxit);
+int32_t ec_mass_apply(ec_handle h, const double *x, double *y);
+int32_t ec_mass_solve(ec_handle h, const double *g, double *y, ec_solve_info *dev_info);
+int32_t ec_mass_counters(ec_handle h, int64_t *solves, int64_t *iters);
 
 /* Replace material mat_id (1..n_mats) of the handle: conductivity and
  * Brauer coefficients (eq. 1).  M_sigma of the conducting edges is rebuilt;

@@ -7,7 +7,7 @@ device memory and streams from torch.
 """
 from ._lib import (EC_ERR_ARG, EC_ERR_BREAKDOWN, EC_ERR_CFL, EC_ERR_HIP,  # noqa
                    EC_ERR_NONFINITE, EC_ERR_NOT_CONVERGED, EC_ERR_SINGULAR_PROJ, EC_ERR_STATE,
-                   EC_OK, MAX_WINDOW, OP_KC_KCN, OP_KCN_T, OP_KN, PREC_FP32_REFINED, PREC_FP64,
+                   EC_OK, MASS_CONSISTENT, MASS_LUMPED, MAX_WINDOW, OP_KC_KCN, OP_KCN_T, OP_KN, PREC_FP32_REFINED, PREC_FP64,
                    SEQ_ADJ, SEQ_CPL, SEQ_SRC, SEQ_USER, STATIC_MAX_NPAD, SV_POD, SV_PREV,
                    SV_SPE, SV_ZERO,
                    ECError, LIB_PATH)

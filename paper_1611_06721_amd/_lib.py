@@ -19,6 +19,7 @@ SEQ_SRC, SEQ_CPL, SEQ_ADJ, SEQ_USER = 0, 1, 2, 3
 SV_ZERO, SV_PREV, SV_SPE, SV_POD = 0, 1, 2, 3
 PREC_FP64, PREC_FP32_REFINED = 0, 1
 OP_KN, OP_KCN_T, OP_KC_KCN = 0, 1, 2
+MASS_LUMPED, MASS_CONSISTENT = 0, 1
 MAX_WINDOW = 20
 STATIC_MAX_NPAD = 1195904
 
@@ -99,6 +100,10 @@ SIGNATURES = {
     "ec_cfl_estimate": (C.c_int32, [_H, _P, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                     C.c_int32, _P, _P]),
     "ec_set_adaptive_dt": (C.c_int32, [_H, _P, C.c_double]),
+    "ec_set_mass": (C.c_int32, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32]),
+    "ec_mass_apply": (C.c_int32, [_H, _P, _P]),
+    "ec_mass_solve": (C.c_int32, [_H, _P, _P, _P]),
+    "ec_mass_counters": (C.c_int32, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "ec_clock": (C.c_int32, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                              C.POINTER(C.c_double)]),
     "ec_adjoint_sizes": (C.c_int32, [_H, C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),

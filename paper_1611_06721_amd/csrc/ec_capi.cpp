@@ -87,6 +87,22 @@ struct ec_problem {
     // stability estimate: the power iterate (compact), the cell records of
     // the operator and the cell pass's partials
     double *cvec2_d = nullptr, *cellv_d = nullptr, *part_cell = nullptr;
+    // consistent conductivity matrix (ELL over the compact conducting edges,
+    // built on the host from the materials) and the solves with it
+    std::vector<int> m_idx;
+    std::vector<double> m_val, m_dinv;
+    double m_hscale = 0.0;
+    int mass_kind = EC_MASS_LUMPED, mass_method = EC_SV_SPE, mass_win = 8, mass_maxit = 200;
+    double mass_rtol = 1e-10;
+    int mass_hint = 16;
+    int64_t ldc = 0;
+    int *m_idx_d = nullptr;
+    double *m_val_d = nullptr, *m_dinv_d = nullptr;
+    double *m_g = nullptr, *m_y = nullptr, *m_p = nullptr, *m_rb[2] = {}, *m_wb[2] = {},
+           *m_sb[2] = {}, *m_w = nullptr, *m_t2 = nullptr, *m_t4 = nullptr, *m_hist = nullptr;
+    double *m_part = nullptr, *m_part_md = nullptr;
+    CgCtl *m_ctl = nullptr;
+    SeqDev *mseq_d = nullptr;
     Mats *mats_d = nullptr;
     SeqDev *seq_d = nullptr;
     Ctrl *ctrl_d = nullptr;
@@ -159,6 +175,73 @@ static bool aligned(const void *p) { return p && ((uintptr_t)p % 16 == 0); }
 static inline int64_t slot(const ec_problem *h, int c, int i, int j, int k)
 {
     return (int64_t)c * h->S + ((int64_t)k * (h->g.ny + 1) + j) * (h->g.nx + 1) + i;
+}
+
+// Consistent conductivity matrix of the lowest-order edge elements (the
+// last paragraph of Sec. III: a non-diagonal M_c).  In a conducting cell of
+// sides h and conductivity sigma, the four edges of direction c couple with
+// sigma h_a1 h_a2 / h_c times the integrals of products of the bilinear hats
+// of the transverse face: 1/9 (the edge itself), 1/18 (a side apart), 1/36
+// (diagonal); row sums are the lumped FIT M_sigma.  Rows over the compact
+// conducting-edge list, at most kMassNnz entries each, ELL layout.
+static void mass_build(ec_problem *h)
+{
+    const int nc = h->nc;
+    const int px = h->g.px, py = h->g.py;
+    const int64_t S = h->S;
+    std::vector<int> pos(h->npad, -1);
+    for (int t = 0; t < nc; ++t) pos[h->cslot[t]] = t;
+    std::vector<int> cols((size_t)nc * kMassNnz, -1), cnt(nc, 0);
+    std::vector<double> vals((size_t)nc * kMassNnz, 0.0);
+    const double hh[3] = {h->g.hx, h->g.hy, h->g.hz};
+    const double w4[4] = {1.0 / 9.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0};
+    const int nx = h->g.nx, ny = h->g.ny, nz = h->g.nz;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int m = h->cmat[((int64_t)k * ny + j) * nx + i];
+                if (!m) continue;
+                const double sig = h->mats.sig[m];
+                for (int c = 0; c < 3; ++c) {
+                    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+                    const double scale = sig * hh[a1] * hh[a2] / hh[c];
+                    int e4[4];
+                    for (int q = 0; q < 4; ++q) {
+                        int nd[3] = {i, j, k};
+                        nd[a1] += q & 1;
+                        nd[a2] += q >> 1;
+                        e4[q] = pos[c * S + ((int64_t)nd[2] * py + nd[1]) * px + nd[0]];
+                    }
+                    for (int e = 0; e < 4; ++e)
+                        for (int f = 0; f < 4; ++f) {
+                            const int row = e4[e], col = e4[f];
+                            if (row < 0 || col < 0) continue;
+                            const double v = scale * w4[((e ^ f) & 1) + 2 * (((e ^ f) >> 1) & 1)];
+                            int q = 0;
+                            while (q < cnt[row] && cols[(size_t)row * kMassNnz + q] != col) ++q;
+                            if (q == cnt[row]) {
+                                cols[(size_t)row * kMassNnz + q] = col;
+                                ++cnt[row];
+                            }
+                            vals[(size_t)row * kMassNnz + q] += v;
+                        }
+                }
+            }
+    h->m_idx.assign((size_t)std::max(nc, 1) * kMassNnz, -1);
+    h->m_val.assign((size_t)std::max(nc, 1) * kMassNnz, 0.0);
+    h->m_dinv.assign(std::max(nc, 1), 0.0);
+    h->m_hscale = 0.0;
+    for (int e = 0; e < nc; ++e)
+        for (int q = 0; q < cnt[e]; ++q) {
+            const int col = cols[(size_t)e * kMassNnz + q];
+            const double v = vals[(size_t)e * kMassNnz + q];
+            h->m_idx[(size_t)q * nc + e] = col;
+            h->m_val[(size_t)q * nc + e] = v;
+            if (col == e) {
+                h->m_dinv[e] = 1.0 / v;
+                h->m_hscale = std::max(h->m_hscale, v);
+            }
+        }
 }
 
 static int32_t assemble(ec_problem *h, const ec_grid *grid, const ec_materials *mat,
@@ -272,6 +355,7 @@ static int32_t assemble(ec_problem *h, const ec_grid *grid, const ec_materials *
         }
     }
     h->nc = (int)h->cslot.size();
+    mass_build(h);
     // band of nonconducting edges coupled to the conductor (K_cn^T support)
     for (int a = 0; a < 3; ++a) {
         h->band_lo[a] = std::max(0, lo[a] - 1);
@@ -387,6 +471,22 @@ static int64_t layout(ec_problem *h, int cap, char *base)
     h->cvec2_d = (double *)take((int64_t)std::max(h->nc, 1) * 8);
     h->cellv_d = (double *)take(std::max<int64_t>(h->ncell, 1) * kCellRec * 8);
     h->part_cell = (double *)take((h->ncell + 255) / 256 * 8 + 8);
+    {
+        const int64_t nc1 = std::max(h->nc, 1);
+        const int64_t ldc = align_up(nc1, 64);
+        h->m_idx_d = (int *)take(kMassNnz * nc1 * 4);
+        h->m_val_d = (double *)take(kMassNnz * nc1 * 8);
+        h->m_dinv_d = (double *)take(nc1 * 8);
+        double **mv[] = {&h->m_g, &h->m_y, &h->m_p, &h->m_rb[0], &h->m_rb[1], &h->m_wb[0],
+                         &h->m_wb[1], &h->m_sb[0], &h->m_sb[1], &h->m_w, &h->m_t2, &h->m_t4};
+        for (double **v : mv) *v = (double *)take(ldc * 8);
+        h->m_hist = (double *)take(2 * (int64_t)(cap + 1) * ldc * 8);
+        h->m_part = (double *)take(2 * 4 * (int64_t)kMaxBlocks * 8);
+        h->m_part_md = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
+        h->m_ctl = (CgCtl *)take(2 * sizeof(CgCtl));
+        h->mseq_d = (SeqDev *)take(sizeof(SeqDev));
+        h->ldc = ldc;
+    }
     h->mats_d = (Mats *)take(sizeof(Mats));
     h->seq_d = (SeqDev *)take(sizeof(SeqDev) * EC_NSEQ);
     h->ctrl_d = (Ctrl *)take(sizeof(Ctrl));
@@ -462,6 +562,18 @@ static int choose_blocks(ec_problem *h)
     return (int)std::max<int64_t>(b, 8);
 }
 
+// consistent M_c table to the device (bound handles)
+static int32_t mass_upload(ec_problem *h)
+{
+    if (!h->nc) return EC_OK;
+    const size_t n9 = (size_t)h->nc * kMassNnz;
+    HIP_TRY(h, hipMemcpyAsync(h->m_idx_d, h->m_idx.data(), n9 * 4, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(h, hipMemcpyAsync(h->m_val_d, h->m_val.data(), n9 * 8, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(h, hipMemcpyAsync(h->m_dinv_d, h->m_dinv.data(), (size_t)h->nc * 8,
+                              hipMemcpyHostToDevice, h->st));
+    return EC_OK;
+}
+
 // largest diagonal entry of K_n (the Jacobi diagonal of the x, y, z edges)
 static double kn_diag_max(const ec_problem *h)
 {
@@ -502,6 +614,13 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
                                   hipMemcpyHostToDevice, st));
     }
     HIP_TRY(h, hipMemcpyAsync(h->mats_d, &h->mats, sizeof(Mats), hipMemcpyHostToDevice, st));
+    {
+        int32_t rc = mass_upload(h);
+        if (rc) return rc;
+        seq_config(h->mseq_d, EC_SV_SPE, window_cap, window_cap, 1e-4, h->m_hscale, st);
+        seq_reset(h->mseq_d, st);
+        h->mass_win = std::min(h->mass_win, window_cap);
+    }
     Ctrl c{};
     c.one = 1.0;
     c.worst = EC_OK;
@@ -1357,6 +1476,223 @@ extern "C" int32_t ec_apply(ec_handle h, int32_t op, const double *x, double *y)
     return launch_check(h, "apply");
 }
 
+// ------------------------------------------------ consistent M_c solves
+static MassOp mass_op(const ec_problem *h) { return MassOp{h->m_idx_d, h->m_val_d, h->m_dinv_d, h->nc}; }
+
+// basis-product and combination arguments over the mass sequence's compact
+// columns (length n_c, stride ldc)
+static MdArgs mass_md(ec_problem *h)
+{
+    MdArgs m{};
+    m.ld = h->ldc;
+    m.part = h->m_part_md;
+    m.n = h->nc;
+    m.A = h->m_hist;
+    return m;
+}
+
+static LcArgs mass_lc(ec_problem *h, double *part)
+{
+    SeqDev *sd = h->mseq_d;
+    LcArgs l{};
+    l.A = h->m_hist;
+    l.B = h->m_hist + (int64_t)(h->cap + 1) * h->ldc;
+    l.ld = h->ldc;
+    l.kp = &sd->ncol_md;
+    l.cA = sd->cA;
+    l.cB = sd->cB;
+    l.a1 = &sd->a1;
+    l.a2 = &sd->a2;
+    l.part = part;
+    l.n = h->nc;
+    return l;
+}
+
+// Append y (compact, the last solution) to the mass sequence's SPE history:
+// the push of seq_push_args (two Gram-Schmidt passes, coefficient steps in
+// the combinations' blocks, the acceptance test in the slot product, window
+// downdate) with M_c in place of K_n and no grad-div term.
+static void mass_push(ec_problem *h, const double *y)
+{
+    hipStream_t st = h->st;
+    SeqDev *sd = h->mseq_d;
+    double *part = h->m_part_md, *part_hi = part + (int64_t)kMaxWin * kMdBlocks;
+    double *Q = h->m_hist, *MQ = h->m_hist + (int64_t)(h->cap + 1) * h->ldc;
+    MdArgs m = mass_md(h);
+    m.kp = &sd->k;
+    m.a_extra = y;
+    m.B[0] = {y, nullptr};
+    m.nb = 1;
+    m.active = &sd->push_on;
+    LcArgs l1 = mass_lc(h, part_hi);
+    l1.v1 = y;
+    l1.y1 = h->m_w;
+    l1.want_dots = 1;
+    l1.pre_seq = sd;
+    l1.pre_op = OP_SPE_PUSH1;
+    l1.pin = part;
+    LcArgs l2 = l1;
+    l2.v1 = h->m_w;
+    l2.y1 = h->m_t2;
+    l2.want_dots = 0;
+    l2.pre_op = OP_SPE_PUSH2;
+    l2.pin = part_hi;
+    l2.part = part;
+    MdArgs m2 = mass_md(h);
+    m2.kp = &sd->ncol_md;
+    m2.B[0] = {h->m_t4, nullptr};
+    m2.nb = 1;
+    m2.active = &sd->accept;
+    SmallArgs s4{};
+    s4.seq = sd;
+    s4.op = OP_SPE_PUSH4;
+    s4.part = part;
+    s4.nvals = std::min(kMdStride, 2 * h->cap + 2);
+    s4.tol = h->dep_tol;
+    multidot(m, st);
+    lincomb(l1, st);
+    lincomb(l2, st);
+    mass_slots(mass_op(h), h->ldc, h->m_t2, MQ, Q, h->m_t4, &sd->slot_new, sd, part, h->dep_tol,
+               st);
+    multidot(m2, st);
+    small(s4, st);
+    rotate(RotArgs{Q, MQ, sd, h->ldc, h->nc}, st);
+}
+
+// y = M_c^{-1} g (compact vectors) by Jacobi-PCG from zero or from the SPE
+// start of the mass sequence (eq. 10 with M_c), then the push of y.  Eager
+// solves poll the done flag in chunks; a captured solve issues mass_maxit
+// iteration kernels (those after convergence return at once).
+static int32_t mass_solve(ec_problem *h, const double *g, double *y, ec_solve_info *info)
+{
+    hipStream_t st = h->st;
+    SeqDev *sd = h->mseq_d;
+    const bool spe = h->mass_method == EC_SV_SPE;
+    if (spe) {
+        MdArgs m = mass_md(h);
+        m.kp = &sd->k;
+        m.B[0] = {g, nullptr};
+        m.nb = 1;
+        SmallArgs sa{};
+        sa.seq = sd;
+        sa.op = OP_SPE_START;
+        sa.part = h->m_part_md;
+        sa.nvals = std::min(kMdStride, 2 * h->cap + 2);
+        sa.tol = h->dep_tol;
+        sa.info = info;
+        LcArgs l = mass_lc(h, h->m_part_md);
+        l.v2 = {g, nullptr};
+        l.y1 = y;
+        l.y2 = h->m_rb[0];
+        multidot(m, st);
+        small(sa, st);
+        lincomb(l, st);
+    }
+    MassCg a{};
+    a.M = mass_op(h);
+    a.x = y;
+    a.b = g;
+    a.p = h->m_p;
+    for (int i = 0; i < 2; ++i) { a.rb[i] = h->m_rb[i]; a.wb[i] = h->m_wb[i]; a.sb[i] = h->m_sb[i]; }
+    a.ctl = h->m_ctl;
+    a.part = h->m_part;
+    a.blocks = mass_blocks(h->nc);
+    a.rtol = h->mass_rtol;
+    a.maxit = h->mass_maxit;
+    a.mode = spe ? START_DEV : START_ZERO;
+    a.seq = spe ? sd : nullptr;
+    a.info = info;
+    a.ctrl = h->ctrl_d;
+    mass_cg_init(a, st);
+    int issued = 0;
+    if (capturing(h)) {
+        for (; issued < a.maxit; ++issued) mass_cg_iter(a, issued, st);
+    } else {
+        int chunk = std::max(1, h->mass_hint + 1), outstanding = -1, slot = 0;
+        bool done = false;
+        while (!done && issued < a.maxit) {
+            const int c = std::min(chunk, a.maxit - issued);
+            for (int j = 0; j < c; ++j) mass_cg_iter(a, issued + j, st);
+            issued += c;
+            HIP_TRY(h, hipMemcpyAsync(h->pin + 8 * slot, &a.ctl[issued & 1].it, 4 * sizeof(int),
+                                      hipMemcpyDeviceToHost, st));
+            HIP_TRY(h, hipEventRecord(h->ev[slot], st));
+            if (outstanding >= 0) {
+                HIP_TRY(h, hipEventSynchronize(h->ev[outstanding]));
+                done = h->pin[8 * outstanding + 1] != 0;
+            }
+            outstanding = slot;
+            slot ^= 1;
+            chunk = std::min(2 * chunk, 64);
+        }
+        if (outstanding >= 0) {
+            HIP_TRY(h, hipEventSynchronize(h->ev[outstanding]));
+            h->mass_hint = std::max(0, h->pin[8 * outstanding]);
+        }
+    }
+    mass_cg_fin(a, issued, st);
+    if (spe) mass_push(h, y);
+    return launch_check(h, "mass solve");
+}
+
+extern "C" int32_t ec_set_mass(ec_handle h, int32_t kind, int32_t method, int32_t window,
+                               double rtol, int32_t maxit)
+{
+    NEED_BOUND(h);
+    flush_pending(h);
+    if (kind != EC_MASS_LUMPED && kind != EC_MASS_CONSISTENT)
+        return fail(h, EC_ERR_ARG, "unknown conductivity matrix kind %d", kind);
+    if (method != EC_SV_ZERO && method != EC_SV_SPE)
+        return fail(h, EC_ERR_ARG, "M_c solves start from zero or from SPE");
+    if (method == EC_SV_SPE && (window < 1 || window > h->cap))
+        return fail(h, EC_ERR_ARG, "window must be 1..%d", h->cap);
+    if (!(rtol > 0) || maxit < 1) return fail(h, EC_ERR_ARG, "need rtol > 0, maxit >= 1");
+    h->mass_kind = kind;
+    h->mass_method = method;
+    h->mass_win = method == EC_SV_SPE ? window : 1;
+    h->mass_rtol = rtol;
+    h->mass_maxit = maxit;
+    seq_config(h->mseq_d, EC_SV_SPE, h->mass_win, h->mass_win, 1e-4, h->m_hscale, h->st);
+    seq_reset(h->mseq_d, h->st);
+    return launch_check(h, "set mass");
+}
+
+extern "C" int32_t ec_mass_apply(ec_handle h, const double *x, double *y)
+{
+    NEED_BOUND(h);
+    if (!aligned(x) || !aligned(y) || x == y)
+        return fail(h, EC_ERR_ARG, "x, y: distinct 16-byte aligned device pointers");
+    gather_c(h->cslot_d, h->nc, x, h->m_g, h->st);
+    mass_apply(mass_op(h), h->m_g, h->m_y, h->st);
+    scatter_c(h->cslot_d, h->nc, h->m_y, y, h->st);
+    return launch_check(h, "mass apply");
+}
+
+extern "C" int32_t ec_mass_solve(ec_handle h, const double *g, double *y, ec_solve_info *dev_info)
+{
+    NEED_BOUND(h);
+    flush_pending(h);
+    if (!aligned(g) || !aligned(y))
+        return fail(h, EC_ERR_ARG, "g, y must be 16-byte aligned device pointers");
+    if (!h->nc) return fail(h, EC_ERR_ARG, "no conducting edges");
+    gather_c(h->cslot_d, h->nc, g, h->m_g, h->st);
+    int32_t rc = mass_solve(h, h->m_g, h->m_y, dev_info);
+    if (rc) return rc;
+    scatter_c(h->cslot_d, h->nc, h->m_y, y, h->st);
+    return launch_check(h, "mass solve");
+}
+
+extern "C" int32_t ec_mass_counters(ec_handle h, int64_t *solves, int64_t *iters)
+{
+    NEED_BOUND(h);
+    Ctrl c{};
+    HIP_TRY(h, hipMemcpyAsync(&c, h->ctrl_d, sizeof c, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    if (solves) *solves = c.mass_solves;
+    if (iters) *iters = c.mass_iters;
+    return EC_OK;
+}
+
 // -------------------------------------------------------------- step
 // One explicit Euler step: source solve, coupled right-hand side, coupling
 // solve, history pushes, state update.  split (a captured step with a
@@ -1399,7 +1735,17 @@ static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const e
     u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
     u.nc = h->nc; u.A = A; u.sj = h->sj; u.sc = h->sc; u.out = h->ac; u.dt = dt; u.apply = 0;
     u.ctrl = h->ctrl_d;
-    update_c(u, st);
+    if (h->mass_kind == EC_MASS_CONSISTENT && h->nc) {
+        // eq. 6 with a consistent M_c: g on C, M_c y = g (its own sequence),
+        // a_c^m = a_c^{m-1} - dt y
+        u.gout = h->m_g;
+        update_c(u, st);
+        rc = mass_solve(h, h->m_g, h->m_y, nullptr);
+        if (rc) return rc;
+        mass_axpy(h->cslot_d, h->nc, A, h->m_y, h->ctrl_d, h->ac, st);
+    } else {
+        update_c(u, st);
+    }
     if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
     if (split) HIP_TRY(h, hipStreamWaitEvent(st, h->sev[1], 0));
     rc = do_solve(h, EC_SEQ_CPL, meth, o->window, o->pod_kmax, o->pod_eps, h->bcpl, nullptr, h->sc,
@@ -1483,6 +1829,7 @@ static int32_t set_state_impl(ec_problem *h, const double *A, const ec_solve_opt
     fill(h->sj, 0.0, h->npad, st);
     fill(&h->ctrl_d->t, 0.0, 1, st);     // the clock of adaptive steps starts at 0
     for (int s = 0; s < EC_NSEQ; ++s) seq_reset(h->seq_d + s, st);
+    seq_reset(h->mseq_d, st);
     HIP_TRY(h, hipStreamSynchronize(st));
     return launch_check(h, "set state");
 }
@@ -1524,6 +1871,8 @@ extern "C" int32_t ec_counters_reset(ec_handle h)
     HIP_TRY(h, hipStreamSynchronize(h->st));
     c.n_steps = 0;
     for (int s = 0; s < EC_NSEQ; ++s) c.iters[s] = 0;
+    c.mass_solves = 0;
+    c.mass_iters = 0;
     c.worst = EC_OK;
     HIP_TRY(h, hipMemcpyAsync(h->ctrl_d, &c, sizeof c, hipMemcpyHostToDevice, h->st));
     HIP_TRY(h, hipStreamSynchronize(h->st));
@@ -1713,6 +2062,13 @@ extern "C" int32_t ec_set_material(ec_handle h, int32_t mat_id, const ec_materia
     h->mats.k1[mat_id] = m->k1;
     h->mats.k2[mat_id] = m->k2;
     h->mats.k3[mat_id] = m->k3;
+    mass_build(h);
+    {
+        int32_t rc = mass_upload(h);
+        if (rc) return rc;
+        seq_config(h->mseq_d, EC_SV_SPE, h->mass_win, h->mass_win, 1e-4, h->m_hscale, h->st);
+        seq_reset(h->mseq_d, h->st);
+    }
     std::vector<double> ms;
     conductivities(h, nullptr, &ms);
     for (int t = 0; t < h->nc; ++t) h->minv[t] = 1.0 / ms[t];
@@ -1841,6 +2197,8 @@ static int32_t adj_args(ec_problem *h, int64_t n_steps, double dt, int32_t every
     if (!h->has_cond) return fail(h, EC_ERR_ARG, "the adjoint needs a conductor");
     if (h->adapt_lam)
         return fail(h, EC_ERR_STATE, "the adjoint runs fixed steps: ec_set_adaptive_dt(h, NULL, 0)");
+    if (h->mass_kind != EC_MASS_LUMPED)
+        return fail(h, EC_ERR_STATE, "the adjoint uses the lumped (diagonal) M_c");
     if (n_steps < 1 || every < 1) return fail(h, EC_ERR_ARG, "need n_steps >= 1, every >= 1");
     if (!ws || ((uintptr_t)ws % kAlign) != 0)
         return fail(h, EC_ERR_ARG, "adjoint workspace must be 256-byte aligned");
@@ -2344,6 +2702,8 @@ static int32_t batch_check(ec_batch_s *b, const double *dt, double *const *A,
     if (o->graph_iters[0] < 0 || o->graph_iters[1] < 0)
         return fail(nullptr, EC_ERR_ARG, "graph_iters must be >= 0");
     for (size_t i = 0; i < b->inst.size(); ++i) {
+        if (b->inst[i]->mass_kind != EC_MASS_LUMPED)
+            return fail(nullptr, EC_ERR_STATE, "instance %zu: batches use the lumped M_c", i);
         int32_t rc = check_step_args(b->inst[i], dt[i], A[i], o);
         if (rc) return fail(nullptr, rc, "instance %zu: %s", i, b->inst[i]->err.c_str());
     }

@@ -188,4 +188,72 @@ __device__ __forceinline__ void for_tiles(int tiles, int64_t S, F fn)
     }
 }
 
+// ------------------------------------------------ single-reduction PCG
+// State entering kernel i from the reduced partials t = (gamma, delta, rho,
+// bb) of the previous kernel and its record prev.  Same in every block.
+__device__ __forceinline__ CgCtl cg_state(const CgCtl &prev, const double (&t)[4], int i,
+                                          double rtol, int maxit, double &beta)
+{
+    CgCtl c = prev;
+    beta = 0.0;
+    if (prev.done) return c;
+    const double gam = t[0], del = t[1], rho = t[2];
+    double den;
+    if (i == 0) {
+        c.bb = t[3];
+        c.tol2 = rtol * rtol * c.bb;
+        c.rho0 = rho;
+        den = del;
+    } else {
+        beta = gam / prev.gamma;
+        den = del - beta * gam / prev.alpha;
+    }
+    c.gamma = gam;
+    c.rho = rho;
+    c.alpha = gam / den;
+    c.it = i;
+    c.status = EC_OK;
+    if (!(rho == rho) || rho > 1e300) {
+        c.done = 1;
+        c.status = EC_ERR_NONFINITE;
+    } else if (c.bb == 0.0 || rho <= c.tol2) {
+        c.done = 1;
+    } else if (i >= maxit) {
+        c.done = 1;
+        c.status = EC_ERR_NOT_CONVERGED;
+    } else if (!(den > 0.0) || !(gam > 0.0)) {
+        c.done = 1;
+        c.status = EC_ERR_BREAKDOWN;
+    }
+    return c;
+}
+
+// This thread's share of the nb block partials of iteration it (strided
+// loads, summed in the same order as reduce_partials).
+__device__ __forceinline__ void part_load(const double *P, int nb, double (&t)[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = 0.0;
+    // four strides' loads in flight before any is summed (one round trip for
+    // up to 4 x blockDim blocks)
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * (int)blockDim.x) {
+        double v[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * (int)blockDim.x;
+            if (b < nb) {
+                const double2 *p2 = reinterpret_cast<const double2 *>(P + (int64_t)b * 4);
+                const double2 lo = p2[0], hi = p2[1];
+                v[u][0] = lo.x; v[u][1] = lo.y; v[u][2] = hi.x; v[u][3] = hi.y;
+            } else {
+                v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] += v[u][q];
+    }
+}
+
 }  // namespace ec

@@ -102,6 +102,7 @@ struct Ctrl {
     double refine_rr, refine_bb;
     double refine_tol;       // relative tolerance of the next inner FP32 solve
     double t;                // time t_m of the current step (adaptive steps accumulate it)
+    int64_t mass_solves, mass_iters;   // solves with the consistent M_c and their iterations
 };
 
 // ----------------------------------------------------------------- launchers
@@ -325,6 +326,7 @@ struct UpdArgs {
     const double *A;         // state: a_c read on C
     const double *sj, *sc;   // y = sj - sc on N (sc may be nullptr)
     const double *xn;        // alternative N operand (apply mode), may be nullptr
+    double *gout;            // if set: g on C into this compact vector, no state update
     const double *nustate;   // state whose a_c sets nu (nullptr: the operand itself)
     double *out;             // update: a_c^m on C; apply: g on C
     double dt;
@@ -416,5 +418,45 @@ hipStream_t bound_stream(const ec_problem *h);
 int32_t solve_scratch(ec_problem *h, int32_t method, const double *b, double *x,
                       const ec_solve_opts *o, ec_solve_info *info, char *scr, int64_t bytes,
                       hipError_t lookup);
+
+// ----------------------------------------- consistent conductivity matrix
+// M_c of the lowest-order edge elements on the compact conducting-edge list:
+// at most kMassNnz entries per row, ELL columns idx/val[q * nc + e] (idx < 0:
+// unused), dinv = 1 / diag (Jacobi)
+constexpr int kMassNnz = 9;
+struct MassOp {
+    const int *idx;
+    const double *val;
+    const double *dinv;
+    int nc;
+};
+// Jacobi-PCG of M_c y = b (compact vectors; single-reduction form, the
+// record protocol of CgArgs): mode START_ZERO, or START_DEV (seq's start:
+// zero_start, else x and rb[0] hold x0 and b - M x0)
+struct MassCg {
+    MassOp M;
+    double *x;
+    const double *b;
+    double *p, *rb[2], *wb[2], *sb[2];
+    CgCtl *ctl;              // [2]
+    double *part;            // [2][kMaxBlocks][4]
+    int blocks;
+    double rtol;
+    int maxit, mode;
+    SeqDev *seq;
+    ec_solve_info *info;     // may be nullptr
+    Ctrl *ctrl;              // counters (may be nullptr)
+};
+int mass_blocks(int nc);
+void mass_apply(const MassOp &M, const double *x, double *y, hipStream_t st);
+void mass_cg_init(const MassCg &a, hipStream_t st);
+void mass_cg_iter(const MassCg &a, int it, hipStream_t st);
+void mass_cg_fin(const MassCg &a, int iters, hipStream_t st);
+// SPE push slot product for the mass sequence (acceptance test in every block)
+void mass_slots(const MassOp &M, int64_t ld, const double *x, double *ycopy, double *xcopy,
+                double *ypen, const int *slot, SeqDev *sq, const double *pin, double tol,
+                hipStream_t st);
+void mass_axpy(const int *cslot, int nc, const double *A, const double *y, const Ctrl *ctrl,
+               double *out, hipStream_t st);
 
 }  // namespace ec

@@ -103,7 +103,9 @@ __device__ __forceinline__ void update_body(const UpdArgs &a)
     r += __shfl_xor(r, 1, 4);
     r += __shfl_xor(r, 2, 4);
     if (q == 0) {
-        if (a.apply) {
+        if (a.gout) {
+            a.gout[e_idx] = r;
+        } else if (a.apply) {
             a.out[e] = r;
         } else {
             const double dt = a.ctrl ? a.ctrl->dt : a.dt;

@@ -249,6 +249,31 @@ class Problem:
             self._chk(self.lib.ec_clock(self.h, C.byref(m), C.byref(t), C.byref(dt)))
         return m.value, t.value, dt.value
 
+    def set_mass(self, kind, method=L.SV_SPE, window=8, rtol=1e-10, maxit=200):
+        """Conductivity matrix of the step: MASS_LUMPED (diagonal FIT) or
+        MASS_CONSISTENT (edge-element mass, M_c y = g solved every step)."""
+        with self._on_stream():
+            self._chk(self.lib.ec_set_mass(self.h, int(kind), int(method), int(window),
+                                           float(rtol), int(maxit)))
+
+    def mass_apply(self, x, out=None):
+        y = self.zeros() if out is None else out
+        with self._on_stream():
+            self._chk(self.lib.ec_mass_apply(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def mass_solve(self, g, out=None, info=None):
+        y = self.zeros() if out is None else out
+        with self._on_stream():
+            self._chk(self.lib.ec_mass_solve(self.h, _ptr(g), _ptr(y), _ptr(info)))
+        return y
+
+    def mass_counters(self):
+        a, b = C.c_int64(), C.c_int64()
+        with self._on_stream():
+            self._chk(self.lib.ec_mass_counters(self.h, C.byref(a), C.byref(b)))
+        return {"solves": a.value, "iters": b.value}
+
     def set_material(self, mat_id, sigma, k1, k2, k3):
         m = L.Material(float(sigma), float(k1), float(k2), float(k3))
         with self._on_stream():
