@@ -281,6 +281,47 @@ int32_t ec_counters_reset(ec_handle h);
 int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, double rtol,
                double *lambda_max);
 
+/* Implicit Euler step m with Newton's method: the reference the paper
+ * compares the semi-explicit scheme with (Secs. I and IV).  With a_n
+ * eliminated as in eqs. (4)-(5b), the conducting unknowns a^m solve
+ *   F(a) = M_c (a - a^{m-1})/dt + N(a) - S a + K_cn K_n^+ j^m = 0
+ * (N(a) = [C^T M_nu(a) C a]_C, S = K_cn K_n^+ K_cn^T); Newton takes
+ * J d = -F, J = M_c/dt + J_N(a) - S, from a = a^{m-1} until
+ * ||F|| <= newton_rtol ||F(a^{m-1})|| or max_newton iterations, each system
+ * by GMRES(gmres_m) (left-preconditioned by (M_c/dt)^-1, restarted, at most
+ * gmres_max Arnoldi steps per Newton iteration) to gmres_rtol of its
+ * preconditioned right-hand side; every product with J solves K_n^+ once
+ * (from zero, inner_rtol), every Newton iteration once more for s_c(a) (on
+ * the coupling sequence, started as start_method / window say, like the
+ * source solve s_j = K_n^+ j^m on the source sequence); then
+ * a_n^m = s_j - s_c(a^m).  A (device padded) holds a^{m-1} on entry and a^m
+ * on exit; the step counter advances as for ec_step.  Unconditionally
+ * stable: dt is free of the bound of eq. (8).  *info (host, may be NULL)
+ * receives the counts and the first and last ||F|| (status
+ * EC_ERR_NOT_CONVERGED if max_newton was reached first).  Uses the lumped
+ * M_c and a fixed dt (EC_ERR_STATE otherwise); not capturable.
+ * Synchronises (the Newton and GMRES stopping tests read device norms).
+ * With SPE- or POD-started coupling solves the error of s_c(a) lies outside
+ * the window rather than spread like a zero-started solve's, and ||F||
+ * levels off near inner_rtol times the conditioning: keep newton_rtol above
+ * about 100 inner_rtol there. */
+typedef struct {
+    double newton_rtol;
+    int32_t max_newton;
+    int32_t gmres_m;        /* restart length, 1..20 */
+    int32_t gmres_max;      /* Arnoldi steps per Newton iteration */
+    double gmres_rtol;
+    double inner_rtol;      /* K_n^+ solves */
+    int32_t start_method;   /* EC_SV_*: source and coupling solves */
+    int32_t window;
+} ec_implicit_opts;
+typedef struct {
+    int32_t newton_iters, gmres_iters, kn_solves, status;
+    double res0, res;
+} ec_implicit_info;
+int32_t ec_implicit_step(ec_handle h, int64_t m, double dt, double *A, const ec_implicit_opts *o,
+                         ec_implicit_info *info);
+
 /* Device-side estimate of the explicit Euler bound (eq. 8; the paper finds
  * lambda_max by the power method) at state A (device padded; its conducting
  * part sets the reluctivity): `iters` power iterations on

@@ -59,6 +59,17 @@ class SolveInfo(C.Structure):
                 ("pod_info", C.c_double), ("r0_rel", C.c_double)]
 
 
+class ImplicitOpts(C.Structure):
+    _fields_ = [("newton_rtol", C.c_double), ("max_newton", C.c_int32), ("gmres_m", C.c_int32),
+                ("gmres_max", C.c_int32), ("gmres_rtol", C.c_double), ("inner_rtol", C.c_double),
+                ("start_method", C.c_int32), ("window", C.c_int32)]
+
+
+class ImplicitInfo(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("kn_solves", C.c_int32),
+                ("status", C.c_int32), ("res0", C.c_double), ("res", C.c_double)]
+
+
 class StepOpts(C.Structure):
     _fields_ = [("start_method", C.c_int32), ("window", C.c_int32), ("pod_kmax", C.c_int32),
                 ("pod_eps", C.c_double), ("solve", SolveOpts), ("graph_iters", C.c_int32 * 2),
@@ -101,6 +112,8 @@ SIGNATURES = {
                                     C.c_int32, _P, _P]),
     "ec_set_adaptive_dt": (C.c_int32, [_H, _P, C.c_double]),
     "ec_set_mass": (C.c_int32, [_H, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32]),
+    "ec_implicit_step": (C.c_int32, [_H, C.c_int64, C.c_double, _P, C.POINTER(ImplicitOpts),
+                                     C.POINTER(ImplicitInfo)]),
     "ec_mass_apply": (C.c_int32, [_H, _P, _P]),
     "ec_mass_solve": (C.c_int32, [_H, _P, _P, _P]),
     "ec_mass_counters": (C.c_int32, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libec.so")
 SOURCES = ["ec_stencil.hip", "ec_basis.hip", "ec_update.hip", "ec_adjoint.hip", "ec_static.hip",
-           "ec_mass.hip", "ec_capi.cpp"]
+           "ec_mass.hip", "ec_newton.hip", "ec_capi.cpp"]
 ARCH = os.environ.get("EC_OFFLOAD_ARCH", "gfx950")
 
 

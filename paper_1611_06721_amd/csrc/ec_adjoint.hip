@@ -273,6 +273,103 @@ void adj_zero(double *acc, int n, hipStream_t st)
 }
 
 
+// ------------------------------------------------- forward Jacobian J_N v
+// J_N(a) v = [C^T (M_nu(a) C v + dM_nu(a; v) C a)]_C with, per conducting
+// cell, d nu = nu'(s) 2 B . dB (B, dB the cell flux densities of a and v,
+// s = |B|^2) and a face's d M_nu the mean of its two cells' d nu times dual
+// length over area (the derivative of the face-averaged reluctivity).
+// Cell pass over the conductor's bounding box: records nu and d nu.
+__global__ void __launch_bounds__(256)
+    k_jn_cell(Geo g, const Mats *__restrict__ mt, const uint8_t *__restrict__ cmat,
+              const double *__restrict__ a, const double *__restrict__ v, double *cellv, int lo0,
+              int lo1, int lo2, int ex, int ey, int ez)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cnt = (int64_t)ex * ey * ez;
+    if (t >= cnt) return;
+    const int64_t exy = (int64_t)ex * ey;
+    const int kk = (int)(t / exy);
+    const int64_t rem = t - (int64_t)kk * exy;
+    const int jj = (int)(rem / ex), ii = (int)(rem - (int64_t)jj * ex);
+    const int i = ii + lo0, j = jj + lo1, k = kk + lo2;
+    const int64_t c = ((int64_t)k * g.ny + j) * g.nx + i;
+    const int m = cmat[c];
+    if (!m) return;
+    double B[3], dB[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        int q[3] = {i, j, k};
+        const double fa0 = face_flux(g, a, n, q[0], q[1], q[2]);
+        const double fv0 = face_flux(g, v, n, q[0], q[1], q[2]);
+        q[n] += 1;
+        const double fa1 = face_flux(g, a, n, q[0], q[1], q[2]);
+        const double fv1 = face_flux(g, v, n, q[0], q[1], q[2]);
+        B[n] = 0.5 * (fa0 + fa1) / face_area(g, n);
+        dB[n] = 0.5 * (fv0 + fv1) / face_area(g, n);
+    }
+    const double s = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    const double e = exp(mt->k2[m] * s);
+    double *r = cellv + c * kCellRec;
+    r[0] = mt->k1[m] * e + mt->k3[m];
+    r[1] = mt->k1[m] * mt->k2[m] * e * 2.0 * (B[0] * dB[0] + B[1] * dB[1] + B[2] * dB[2]);
+}
+
+// Edge pass: out[e] = sum over the four faces of edge e of
+// sign (M_nu C u + dM_nu C a)_f, with u = v on C and -K_n^+ K_cn^T v on N
+// this is J_N(a) v - S v on the conducting edges (four lanes per edge).
+__global__ void __launch_bounds__(256)
+    k_jn_edge(Geo g, const int *__restrict__ cslot, int nc, const double *__restrict__ cellv,
+              const double *__restrict__ u, const double *__restrict__ a, double *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = t >> 2;
+    const int q = (int)(t & 3);
+    double val = 0.0;
+    if (e < nc) {
+        const int64_t slot = cslot[e];
+        const int c = (int)(slot / g.S);
+        int i, j, k;
+        decode(g, slot - (int64_t)c * g.S, i, j, k);
+        const int c1 = c == 2 ? 0 : c + 1, c2 = c == 0 ? 2 : c - 1;
+        const int n = q < 2 ? c2 : c1;
+        const int sh = q == 1 ? c1 : (q == 3 ? c2 : -1);
+        const double sign = (q == 0 || q == 3) ? 1.0 : -1.0;
+        int f[3] = {i, j, k};
+        if (sh >= 0) f[sh] -= 1;
+        int ca[3] = {f[0], f[1], f[2]};
+        ca[n] -= 1;
+        const int64_t cA = ((int64_t)ca[2] * g.ny + ca[1]) * g.nx + ca[0];
+        const int64_t cB = ((int64_t)f[2] * g.ny + f[1]) * g.nx + f[0];
+        const double *rA = cellv + cA * kCellRec, *rB = cellv + cB * kCellRec;
+        const double geo = face_geo(g, n);
+        const double mnu = geo * 0.5 * (rA[0] + rB[0]);
+        const double dm = geo * 0.5 * (rA[1] + rB[1]);
+        val = sign * (mnu * face_flux(g, u, n, f[0], f[1], f[2]) +
+                      dm * face_flux(g, a, n, f[0], f[1], f[2]));
+    }
+    val += __shfl_xor(val, 1, 64);
+    val += __shfl_xor(val, 2, 64);
+    if (e < nc && q == 0) out[e] = val;
+}
+
+void jn_cell(const Geo &g, const Mats *mt, const uint8_t *cmat, const double *a, const double *v,
+             double *cellv, const int lo[3], const int hi[3], hipStream_t st)
+{
+    const int ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+    const int64_t cnt = (int64_t)ext[0] * ext[1] * ext[2];
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(k_jn_cell, dim3(blocks_for(cnt, 256)), dim3(256), 0, st, g, mt, cmat, a, v,
+                       cellv, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2]);
+}
+
+void jn_edge(const Geo &g, const int *cslot, int nc, const double *cellv, const double *u,
+             const double *a, double *out, hipStream_t st)
+{
+    if (nc <= 0) return;
+    hipLaunchKernelGGL(k_jn_edge, dim3(blocks_for(4 * (int64_t)nc, 256)), dim3(256), 0, st, g,
+                       cslot, nc, cellv, u, a, out);
+}
+
 // ------------------------------------------------- stability estimate (eq. 8)
 // Power method on B = (X^T - S) M_c^{-1}, the transpose of M_c^{-1} (X - S)
 // (X = J_N(a) or K_c(nu(a)); same eigenvalues), on compact conducting-edge

@@ -103,6 +103,13 @@ struct ec_problem {
     double *m_part = nullptr, *m_part_md = nullptr;
     CgCtl *m_ctl = nullptr;
     SeqDev *mseq_d = nullptr;
+    // implicit Euler / Newton: padded Newton state and matrix-product vectors,
+    // compact residual, start, correction and GMRES vectors, the Arnoldi
+    // basis, the GMRES record and partial sums
+    double *i_a = nullptr, *i_v = nullptr, *i_b = nullptr, *i_s = nullptr, *i_u = nullptr;
+    double *i_aold = nullptr, *i_F = nullptr, *i_x = nullptr, *i_w = nullptr, *i_jv = nullptr,
+           *i_t = nullptr, *i_V = nullptr, *i_part = nullptr, *i_pn = nullptr, *i_norm = nullptr;
+    GmDev *gm_d = nullptr;
     Mats *mats_d = nullptr;
     SeqDev *seq_d = nullptr;
     Ctrl *ctrl_d = nullptr;
@@ -486,6 +493,15 @@ static int64_t layout(ec_problem *h, int cap, char *base)
         h->m_ctl = (CgCtl *)take(2 * sizeof(CgCtl));
         h->mseq_d = (SeqDev *)take(sizeof(SeqDev));
         h->ldc = ldc;
+        double **ip[] = {&h->i_a, &h->i_v, &h->i_b, &h->i_s, &h->i_u};
+        for (double **v : ip) *v = (double *)take(ld * 8);
+        double **ic[] = {&h->i_aold, &h->i_F, &h->i_x, &h->i_w, &h->i_jv, &h->i_t};
+        for (double **v : ic) *v = (double *)take(ldc * 8);
+        h->i_V = (double *)take((int64_t)(kGmMax + 1) * ldc * 8);
+        h->i_part = (double *)take((int64_t)kMdBlocks * kMdStride * 8);
+        h->i_pn = (double *)take(256 * 8);
+        h->i_norm = (double *)take(8 * 8);
+        h->gm_d = (GmDev *)take(sizeof(GmDev));
     }
     h->mats_d = (Mats *)take(sizeof(Mats));
     h->seq_d = (SeqDev *)take(sizeof(SeqDev) * EC_NSEQ);
@@ -1931,6 +1947,184 @@ extern "C" int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, dou
     *lambda_max = lam;
     if (std::isfinite(lam) && lam > 0.0) h->cfl_lam = lam;
     return launch_check(h, "cfl");
+}
+
+// ------------------------------------------------ implicit Euler / Newton
+// P^-1 J v for column v (compact) into out: v on C and 0 on N (i_v), cell
+// records of J_N(a) in direction v, s = K_n^+ K_cn^T v (zero start, the
+// USER sequence), u = v (+) -s (i_u), (J_N - S) v by the edge pass, then
+// v + dt M_c^-1 (J_N - S) v.
+static int32_t newton_matvec(ec_problem *h, const double *v, double dt, const ec_solve_opts *so,
+                             double *out)
+{
+    hipStream_t st = h->st;
+    const int nc = h->nc;
+    scatter_c(h->cslot_d, nc, v, h->i_v, st);
+    jn_cell(h->g, h->mats_d, h->cmat_d, h->i_a, h->i_v, h->cellv_d, h->bblo, h->bbhi, st);
+    spmv(h->g, h->i_v, h->i_b, h->band_lo, h->band_hi, st);
+    int32_t rc = do_solve(h, EC_SEQ_USER, EC_SV_ZERO, 1, 1, 0.0, h->i_b, nullptr, h->i_s, so,
+                          nullptr, false);
+    if (rc) return rc;
+    negate(h->i_s, h->i_u, h->npad, st);
+    scatter_c(h->cslot_d, nc, v, h->i_u, st);
+    jn_edge(h->g, h->cslot_d, nc, h->cellv_d, h->i_u, h->i_a, h->i_jv, st);
+    gm_precond(nc, v, h->i_jv, h->minv_d, dt, out, st);
+    return EC_OK;
+}
+
+static int32_t read_dev(ec_problem *h, const void *src, size_t bytes, int slot)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->pin + 24 + slot, src, bytes, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(h, hipStreamSynchronize(h->st));
+    return EC_OK;
+}
+
+// One implicit Euler step m (the paper's reference method): Newton on the
+// Schur form of eq. (3) (a_n eliminated as in eqs. 4-5b):
+//   F(a) = M_c (a - a_old)/dt + g(a, s_j - s_c(a)),  s_j = K_n^+ j^m,
+//   s_c(a) = K_n^+ K_cn^T a, g the conducting rows of K(nu(a)) (eq. 6's g),
+// J d = -F with J = M_c/dt + J_N(a) - S by GMRES(m) left-preconditioned with
+// (M_c/dt)^-1, a += d, until ||F|| <= newton_rtol ||F(a_old)||.  The source
+// and coupling solves run on the SRC and CPL sequences with the options'
+// start vector (consecutive Newton iterates converge, so SPE extrapolates
+// their s_c); the products' K_n^+ solves start from zero.  Host control
+// reads ||F|| after each Newton iteration and GMRES's convergence flag after
+// each Arnoldi step; all arithmetic runs in kernels.
+extern "C" int32_t ec_implicit_step(ec_handle h, int64_t m, double dt, double *A,
+                                    const ec_implicit_opts *o, ec_implicit_info *info)
+{
+    NEED_BOUND(h);
+    flush_pending(h);
+    if (!aligned(A) || !o || !(dt > 0) || !std::isfinite(dt))
+        return fail(h, EC_ERR_ARG, "need an aligned A, opts and dt > 0");
+    if (!(o->newton_rtol > 0) || o->max_newton < 1 || o->gmres_m < 1 || o->gmres_m > kGmMax ||
+        o->gmres_max < 1 || !(o->gmres_rtol > 0) || !(o->inner_rtol > 0))
+        return fail(h, EC_ERR_ARG, "newton_rtol, gmres_rtol, inner_rtol > 0; max_newton, "
+                                   "gmres_max >= 1; 1 <= gmres_m <= %d", kGmMax);
+    const int meth = o->start_method;
+    if (meth < EC_SV_ZERO || meth > EC_SV_POD ||
+        ((meth == EC_SV_SPE || meth == EC_SV_POD) && (o->window < 1 || o->window > h->cap)))
+        return fail(h, EC_ERR_ARG, "start method and window 1..%d", h->cap);
+    if (!h->has_cond) return fail(h, EC_ERR_ARG, "the implicit step needs a conductor");
+    if (h->mass_kind != EC_MASS_LUMPED || h->adapt_lam)
+        return fail(h, EC_ERR_STATE, "the implicit step uses the lumped M_c and a fixed dt");
+    if (capturing(h)) return fail(h, EC_ERR_STATE, "the implicit step is not captured");
+    hipStream_t st = h->st;
+    const int nc = h->nc;
+    const ec_solve_opts so{o->inner_rtol, 1000000, EC_PREC_FP64, 0.0, 0, 0};
+    const int win = (meth == EC_SV_SPE || meth == EC_SV_POD) ? o->window : 1;
+    step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st);
+    int32_t rc = do_solve(h, EC_SEQ_SRC, meth, win, win, 1e-4, h->xs_d, &h->ctrl_d->scale, h->sj,
+                          &so, nullptr, false);
+    if (rc) return rc;
+    if (meth == EC_SV_SPE || meth == EC_SV_POD) seq_push(h, EC_SEQ_SRC, meth, h->sj);
+    adj_cell_init(h->cellv_d, h->ncell, h->mats.nu0, st);   // air cells: nu0, no d nu
+    fill(h->i_a, 0.0, h->npad, st);
+    copy_c(h->cslot_d, nc, A, h->i_a, st);
+    gather_c(h->cslot_d, nc, A, h->i_aold, st);
+    fill(h->i_v, 0.0, h->npad, st);
+    fill(h->i_b, 0.0, h->npad, st);
+    int newton = 0, gm_total = 0, kn = 1;
+    double f0 = -1.0, fn = 0.0;
+    const int64_t ldc = h->ldc;
+    GmDev *gm = h->gm_d;
+    for (;;) {
+        // s_c(a) and F(a)
+        spmv(h->g, h->i_a, h->bcpl, h->band_lo, h->band_hi, st);
+        rc = do_solve(h, EC_SEQ_CPL, meth, win, win, 1e-4, h->bcpl, nullptr, h->sc, &so, nullptr,
+                      false);
+        if (rc) return rc;
+        if (meth == EC_SV_SPE || meth == EC_SV_POD) seq_push(h, EC_SEQ_CPL, meth, h->sc);
+        ++kn;
+        UpdArgs u{};
+        u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
+        u.nc = nc; u.A = h->i_a; u.sj = h->sj; u.sc = h->sc; u.gout = h->i_F; u.ctrl = h->ctrl_d;
+        update_c(u, st);
+        newton_residual(nc, h->cslot_d, h->i_a, h->i_aold, h->minv_d, dt, h->i_F, st);
+        nrm2_fin(h->i_pn, nrm2_part(nc, h->i_F, h->i_pn, st), h->i_norm, st);
+        double nv = 0.0;
+        rc = read_dev(h, h->i_norm, 8, 0);
+        if (rc) return rc;
+        std::memcpy(&nv, h->pin + 24, 8);
+        fn = nv;
+        if (f0 < 0.0) f0 = fn;
+        if (!(fn > o->newton_rtol * f0) || newton >= o->max_newton) break;
+        // GMRES(m): P^-1 J d = -P^-1 F from d = 0
+        fill(h->i_x, 0.0, nc, st);
+        gm_precond(nc, nullptr, h->i_F, h->minv_d, dt, h->i_t, st);     // -P^-1 F
+        HIP_TRY(h, hipMemcpyAsync(h->i_w, h->i_t, (size_t)nc * 8, hipMemcpyDeviceToDevice, st));
+        bool first = true;
+        for (;;) {
+            gm_begin(gm, h->i_pn, nrm2_part(nc, h->i_w, h->i_pn, st), first ? 1 : 0, o->gmres_rtol,
+                     st);
+            first = false;
+            LcArgs l0{};
+            l0.A = h->i_V; l0.ld = ldc; l0.kp = &gm->ncol; l0.cA = gm->coef; l0.a1 = &gm->a1;
+            l0.v1 = h->i_w; l0.slot = &gm->slot; l0.part = h->i_part; l0.n = nc;
+            lincomb(l0, st);
+            rc = read_dev(h, &gm->conv, 4, 4);
+            if (rc) return rc;
+            if (h->pin[28]) break;
+            int jn = 0;
+            bool conv = false;
+            for (int j = 0; j < o->gmres_m && gm_total < o->gmres_max; ++j) {
+                rc = newton_matvec(h, h->i_V + (int64_t)j * ldc, dt, &so, h->i_w);
+                if (rc) return rc;
+                ++kn;
+                MdArgs md{};
+                md.A = h->i_V; md.ld = ldc; md.kfix = j + 1; md.B[0] = {h->i_w, nullptr}; md.nb = 1;
+                md.part = h->i_part; md.n = nc;
+                multidot(md, st);
+                gm_orth1(gm, h->i_part, j, st);
+                LcArgs l1{};
+                l1.A = h->i_V; l1.ld = ldc; l1.kp = &gm->ncol; l1.cA = gm->coef; l1.a1 = &gm->a1;
+                l1.v1 = h->i_w; l1.y1 = h->i_w; l1.want_dots = 1; l1.part = h->i_part; l1.n = nc;
+                lincomb(l1, st);
+                gm_orth2(gm, h->i_part, j, st);
+                LcArgs l2 = l1;
+                l2.y1 = nullptr;
+                l2.slot = &gm->slot;
+                l2.want_dots = 0;
+                lincomb(l2, st);
+                ++jn;
+                ++gm_total;
+                rc = read_dev(h, &gm->conv, 4, 4);
+                if (rc) return rc;
+                if (h->pin[28]) {
+                    conv = true;
+                    break;
+                }
+            }
+            gm_solve(gm, jn, st);
+            LcArgs lx{};
+            lx.A = h->i_V; lx.ld = ldc; lx.kp = &gm->ncol; lx.cA = gm->coef; lx.a1 = &gm->a1;
+            lx.v1 = h->i_x; lx.y1 = h->i_x; lx.part = h->i_part; lx.n = nc;
+            lincomb(lx, st);
+            if (conv || gm_total >= o->gmres_max) break;
+            // restart on the true residual -P^-1 F - P^-1 J d
+            rc = newton_matvec(h, h->i_x, dt, &so, h->i_w);
+            if (rc) return rc;
+            ++kn;
+            vsub(nc, h->i_t, h->i_w, h->i_w, st);
+        }
+        newton_update(nc, h->cslot_d, h->i_x, h->i_a, st);
+        ++newton;
+    }
+    // the new state: a on C, s_j - s_c(a) on N (s_c of the last Newton iterate)
+    finish_state(h->g, A, h->i_a, h->sj, h->sc, h->ctrl_d, 1, st);
+    rc = launch_check(h, "implicit step");
+    if (rc) return rc;
+    if (info) {
+        info->newton_iters = newton;
+        info->gmres_iters = gm_total;
+        info->kn_solves = kn;
+        info->status = std::isfinite(fn) ? (fn > o->newton_rtol * f0 ? EC_ERR_NOT_CONVERGED : EC_OK)
+                                         : EC_ERR_NONFINITE;
+        info->res0 = f0;
+        info->res = fn;
+    }
+    HIP_TRY(h, hipStreamSynchronize(st));
+    return EC_OK;
 }
 
 // ------------------------------------------------- stability estimate

@@ -459,4 +459,34 @@ void mass_slots(const MassOp &M, int64_t ld, const double *x, double *ycopy, dou
 void mass_axpy(const int *cslot, int nc, const double *A, const double *y, const Ctrl *ctrl,
                double *out, hipStream_t st);
 
+// ------------------------------------------------ implicit Euler / Newton
+// forward Jacobian: cell records (nu, d nu) of J_N(a) in direction v, and
+// out = J_N(a) v - S v on the conducting edges from u = v (+) -K_n^+ K_cn^T v
+void jn_cell(const Geo &g, const Mats *mt, const uint8_t *cmat, const double *a, const double *v,
+             double *cellv, const int lo[3], const int hi[3], hipStream_t st);
+void jn_edge(const Geo &g, const int *cslot, int nc, const double *cellv, const double *u,
+             const double *a, double *out, hipStream_t st);
+// GMRES(m) record: restart length at most kGmMax (its m + 1 basis columns fit
+// the basis products' column limit kMaxWin)
+constexpr int kGmMax = 20;
+struct GmDev {
+    int ncol, slot, conv, pad;
+    double beta, target, res, a1;
+    double H[(kGmMax + 1) * kGmMax];   // rotated Hessenberg matrix, row i at i * kGmMax
+    double cs[kGmMax], sn[kGmMax], g[kGmMax + 1];
+    double h1[kGmMax + 1], coef[kGmMax + 1];
+};
+int nrm2_part(int n, const double *x, double *part, hipStream_t st);
+void nrm2_fin(const double *part, int nb, double *out, hipStream_t st);
+void gm_begin(GmDev *gm, const double *part, int nb, int first, double rtol, hipStream_t st);
+void gm_orth1(GmDev *gm, const double *part, int j, hipStream_t st);
+void gm_orth2(GmDev *gm, const double *part, int j, hipStream_t st);
+void gm_solve(GmDev *gm, int jn, hipStream_t st);
+void gm_precond(int nc, const double *v, const double *jv, const double *minv, double dt,
+                double *w, hipStream_t st);
+void newton_residual(int nc, const int *cslot, const double *a, const double *a_old,
+                     const double *minv, double dt, double *F, hipStream_t st);
+void newton_update(int nc, const int *cslot, const double *d, double *a, hipStream_t st);
+void vsub(int n, const double *x, const double *y, double *out, hipStream_t st);
+
 }  // namespace ec

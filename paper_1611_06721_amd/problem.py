@@ -249,6 +249,21 @@ class Problem:
             self._chk(self.lib.ec_clock(self.h, C.byref(m), C.byref(t), C.byref(dt)))
         return m.value, t.value, dt.value
 
+    def implicit_step(self, A, m, dt, newton_rtol=1e-10, max_newton=20, gmres_m=20,
+                      gmres_max=400, gmres_rtol=1e-8, inner_rtol=1e-10, method=L.SV_SPE,
+                      window=8):
+        """One implicit Euler step with Newton-GMRES (ec_implicit_step);
+        returns the step's counts and residual norms."""
+        o = L.ImplicitOpts(float(newton_rtol), int(max_newton), int(gmres_m), int(gmres_max),
+                           float(gmres_rtol), float(inner_rtol), int(method), int(window))
+        inf = L.ImplicitInfo()
+        with self._on_stream():
+            self._chk(self.lib.ec_implicit_step(self.h, int(m), float(dt), _ptr(A), C.byref(o),
+                                                C.byref(inf)))
+        return {"newton_iters": inf.newton_iters, "gmres_iters": inf.gmres_iters,
+                "kn_solves": inf.kn_solves, "status": inf.status, "res0": inf.res0,
+                "res": inf.res}
+
     def set_mass(self, kind, method=L.SV_SPE, window=8, rtol=1e-10, maxit=200):
         """Conductivity matrix of the step: MASS_LUMPED (diagonal FIT) or
         MASS_CONSISTENT (edge-element mass, M_c y = g solved every step)."""
