@@ -487,18 +487,45 @@ __device__ __forceinline__ void cg_update(const CgArgs<T> &a, int it, const CgCt
         for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
 }
 
+// Raw buffer view of a vector of `count` elements for the hoisted iteration:
+// a load at element index e reads element e when 0 <= e < count and returns
+// 0 otherwise without touching memory (the range check of buffer loads: a
+// negative index wraps to an unsigned byte offset beyond the buffer).  Byte
+// offsets are 32-bit: count * sizeof(T) < 2^31 (checked where the hoisted
+// form is chosen).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_view(const void *p, int64_t bytes)
+{
+    // dword 3 of a raw (untyped) buffer resource on gfx9-family targets
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+
+// the hoisted form runs only with one tile per block, so on at most
+// kMaxBlocks tiles: its vectors stay far below 2^31 bytes
+static_assert((int64_t)kMaxBlocks * kTile * 3 * 8 < (1ll << 31), "buffer offsets are 32-bit");
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int e)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, 0));
+}
+
 // The iteration with the node's stencil inputs loaded before the decision,
 // for launches where every block sweeps at most one tile: r, w, s at the 24
 // stencil positions and the node's own p, x are in flight while the block
 // reduces the previous partials, then t = D^-1 (r - alpha (w + beta s)), the
-// curl-curl and the update use exactly the expressions of cg_update.
-template <typename T>
-__device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int nprev,
-                                                CgCtl &s_c, double &s_beta, int bid)
+// curl-curl and the update use exactly the expressions of cg_update.  The
+// loads go through range-checked buffer views: a stencil position outside
+// the vectors (only ever feeding Dirichlet/padding outputs) reads 0, one
+// 32-bit index per position instead of a clamped 64-bit address per load.
+template <typename T, bool FIRST>
+__device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, int nprev,
+                                                  CgCtl &s_c, double &s_beta, int bid)
 {
     const Geo &g = a.g;
     const int64_t S = g.S;
-    const bool first = it == 0;
     const T *rc = a.rb[it & 1], *wc = a.wb[it & 1], *sp = a.sb[(it + 1) & 1];
     T *rn = a.rb[(it + 1) & 1], *wn = a.wb[(it + 1) & 1], *sc = a.sb[it & 1];
     double t[4];
@@ -506,32 +533,29 @@ __device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int 
     // this block's tile (the map of for_tiles_b with one tile per block)
     const int tpx = (a.tiles + 7) >> 3, xcd = bid & 7, loc = bid >> 3;
     const int tile = xcd * tpx + loc;
-    const int64_t n = (int64_t)tile * kTile + threadIdx.x;
+    const int n = tile * kTile + (int)threadIdx.x;
     const bool valid = loc < tpx && tile < a.tiles && n < S;
+    const int64_t bytes = 3 * S * (int64_t)sizeof(T);
+    const __amdgpu_buffer_rsrc_t vr_b = buf_view(rc, bytes), vw_b = buf_view(wc, bytes),
+                                 vs_b = buf_view(sp, bytes), vp_b = buf_view(a.p, bytes),
+                                 vx_b = buf_view(a.x, bytes);
     // stencil positions in the order of curlcurl_node: 8 of x, 8 of y, 8 of z
-    const int64_t oi = 1, oj = g.px, ok = (int64_t)g.px * g.py, last = 3 * S - 1;
-    const int64_t off[24] = {0, ok, -ok, ok - oi, -oi, oj, -oj, oj - oi,
-                             0, ok, -ok, -oj, ok - oj, oi, oi - oj, -oi,
-                             0, oj, oj - ok, -ok, -oj, oi, oi - ok, -oi};
+    const int oi = 1, oj = g.px, ok = g.px * g.py, Si = (int)S;
+    const int off[24] = {0, ok, -ok, ok - oi, -oi, oj, -oj, oj - oi,
+                         0, ok, -ok, -oj, ok - oj, oi, oi - oj, -oi,
+                         0, oj, oj - ok, -ok, -oj, oi, oi - ok, -oi};
     T vr[24], vw[24], vs[24], op[3], ox[3];
 #pragma unroll
     for (int q = 0; q < 24; ++q) {
-        vr[q] = vw[q] = vs[q] = (T)0;
-        if (valid) {
-            int64_t ix = (int64_t)(q >> 3) * S + n + off[q];
-            ix = ix < 0 ? 0 : (ix > last ? last : ix);
-            vr[q] = rc[ix];
-            vw[q] = wc[ix];
-            if (!first) vs[q] = sp[ix];
-        }
+        const int e = (q >> 3) * Si + n + off[q];
+        vr[q] = buf_load<T>(vr_b, e);
+        vw[q] = buf_load<T>(vw_b, e);
+        vs[q] = FIRST ? (T)0 : buf_load<T>(vs_b, e);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        op[c] = ox[c] = (T)0;
-        if (valid) {
-            if (!first) op[c] = a.p[c * S + n];
-            ox[c] = a.x[c * S + n];
-        }
+        op[c] = FIRST ? (T)0 : buf_load<T>(vp_b, c * Si + n);
+        ox[c] = buf_load<T>(vx_b, c * Si + n);
     }
     if (cg_decide<T>(a, it, t, s_c, s_beta, bid)) return true;
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
@@ -544,7 +568,7 @@ __device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int 
 #pragma unroll
         for (int q = 0; q < 24; ++q) {
             const T d = (T)dsel(dd, q >> 3);
-            tv[q] = first ? d * (vr[q] - ta * vw[q]) : d * (vr[q] - ta * (vw[q] + tb * vs[q]));
+            tv[q] = FIRST ? d * (vr[q] - ta * vw[q]) : d * (vr[q] - ta * (vw[q] + tb * vs[q]));
         }
         const T x0 = tv[0], x_kp = tv[1], x_km = tv[2], x_im_kp = tv[3], x_im = tv[4],
                 x_jp = tv[5], x_jm = tv[6], x_im_jp = tv[7];
@@ -570,8 +594,8 @@ __device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int 
             const int64_t ix = c * S + n;
             const T d = (T)dsel(dd, c);
             const T rv = vr[8 * c], wv = vw[8 * c];
-            const T si = first ? wv : wv + tb * vs[8 * c];
-            const T pi = first ? d * rv : d * rv + tb * op[c];
+            const T si = FIRST ? wv : wv + tb * vs[8 * c];
+            const T pi = FIRST ? d * rv : d * rv + tb * op[c];
             a.x[ix] = ox[c] + ta * pi;
             a.p[ix] = pi;
             sc[ix] = si;
@@ -591,6 +615,14 @@ __device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int 
         for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
     }
     return false;
+}
+
+template <typename T>
+__device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int nprev,
+                                                CgCtl &s_c, double &s_beta, int bid)
+{
+    return it == 0 ? cg_iter_hoisted_t<T, true>(a, it, nprev, s_c, s_beta, bid)
+                   : cg_iter_hoisted_t<T, false>(a, it, nprev, s_c, s_beta, bid);
 }
 
 // One tile per block on a grid of nb blocks: the hoisted form applies (the
