@@ -36,10 +36,45 @@ __device__ __forceinline__ int edge_cls(const Geo &g, int c, int i, int j, int k
     return inC ? 1 : 2;
 }
 
+// v of the lane that the DPP control CTRL selects (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint2 u = __builtin_bit_cast(uint2, v);
+    uint2 r;
+    r.x = (unsigned)__builtin_amdgcn_mov_dpp((int)u.x, CTRL, 0xF, 0xF, false);
+    r.y = (unsigned)__builtin_amdgcn_mov_dpp((int)u.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane; every
+// lane of the wave must be active.  Fixed order: pairs of lanes (lane ^ 1,
+// then lane ^ 2) and the two halves of each 8-lane and 16-lane row by DPP
+// (VALU, no LDS round trip), then row pairs and wave halves by the gfx950
+// lane swaps (v_permlane16_swap / v_permlane32_swap).  Each step adds the
+// same two operands in both partner lanes, so all lanes agree bitwise.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of the 8 lanes
+    v += dpp_f64<0x140>(v);   // row_mirror: the other 8 lanes of the row
+    {
+        const uint2 u = __builtin_bit_cast(uint2, v);
+        const auto lo = __builtin_amdgcn_permlane16_swap(u.x, u.x, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(u.y, u.y, false, false);
+        const double a = __builtin_bit_cast(double, make_uint2(lo[0], hi[0]));
+        const double b = __builtin_bit_cast(double, make_uint2(lo[1], hi[1]));
+        v = a + b;            // even row + odd row of each row pair
+    }
+    {
+        const uint2 u = __builtin_bit_cast(uint2, v);
+        const auto lo = __builtin_amdgcn_permlane32_swap(u.x, u.x, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(u.y, u.y, false, false);
+        const double a = __builtin_bit_cast(double, make_uint2(lo[0], hi[0]));
+        const double b = __builtin_bit_cast(double, make_uint2(lo[1], hi[1]));
+        v = a + b;            // lower half + upper half
+    }
     return v;
 }
 

@@ -520,6 +520,8 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int e)
 // loads go through range-checked buffer views: a stencil position outside
 // the vectors (only ever feeding Dirichlet/padding outputs) reads 0, one
 // 32-bit index per position instead of a clamped 64-bit address per load.
+static_assert(kTile == 256, "the hoisted iteration reduces over four waves");
+
 template <typename T, bool FIRST>
 __device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, int nprev,
                                                   CgCtl &s_c, double &s_beta, int bid)
@@ -557,9 +559,36 @@ __device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, in
         op[c] = FIRST ? (T)0 : buf_load<T>(vp_b, c * Si + n);
         ox[c] = buf_load<T>(vx_b, c * Si + n);
     }
-    if (cg_decide<T>(a, it, t, s_c, s_beta, bid)) return true;
+    // the previous partials: wave sums, the four waves' sums in a fixed order
+    // read back by every thread (one barrier), and the decision taken in
+    // every lane (same inputs, same result: no broadcast); block 0 stores
+    // the record, thread 0 keeps it in s_c for the caller
+    __shared__ double s_in[4][4], s_out[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = wave_sum(t[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_in[q][wv] = t[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = ((s_in[q][0] + s_in[q][1]) + s_in[q][2]) + s_in[q][3];
+    double beta;
+    const double rtol = (it == 0 && a.rtol_dev) ? *a.rtol_dev : a.rtol;
+    const CgCtl c = cg_state(a.ctl[it & 1], t, it, rtol, a.maxit, beta);
+    if (threadIdx.x == 0) {
+        s_c = c;
+        s_beta = beta;
+        if (bid == 0) {
+            CgCtl o = c;
+            if (!o.done) o.it = it + 1;   // iterations completed after this one
+            a.ctl[(it + 1) & 1] = o;
+        }
+    }
+    if (c.done) return true;
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
-    const T ta = (T)s_c.alpha, tb = (T)s_beta;
+    const T ta = (T)c.alpha, tb = (T)beta;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
         int i, j, k;
@@ -609,10 +638,20 @@ __device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, in
             v[2] += (double)r1 * (double)r1;
         }
     }
-    block_sum<4>(v);
+    // this iteration's partials: wave sums, then thread 0 adds the four
+    // waves' sums in a fixed order (one barrier)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_out[q][wv] = v[q];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double *Pout = a.part + (int64_t)((it + 1) & 1) * 4 * kMaxBlocks;
-        for (int q = 0; q < 4; ++q) Pout[(int64_t)bid * 4 + q] = v[q];
+        for (int q = 0; q < 4; ++q)
+            Pout[(int64_t)bid * 4 + q] =
+                ((s_out[q][0] + s_out[q][1]) + s_out[q][2]) + s_out[q][3];
     }
     return false;
 }
