@@ -2649,7 +2649,7 @@ static int32_t batch_apply_tiles(ec_batch_s *b, int f)
     b->tiles_per_block = f;
     b->one_tile = true;
     for (ec_problem *h : b->inst)
-        if ((h->cg_blocks >> 3) < ((h->tiles + 7) >> 3)) b->one_tile = false;
+        if ((h->cg_blocks >> 3) < ((h->tiles + 7) >> 3) || h->g.px > kHaloMax) b->one_tile = false;
     ec_problem *h0 = b->inst[0];
     HIP_TRY(h0, hipMemcpyAsync(b->inst_d, im.data(), im.size() * 4, hipMemcpyHostToDevice, b->st));
     HIP_TRY(h0, hipMemcpyAsync(b->off_d, of.data(), of.size() * 4, hipMemcpyHostToDevice, b->st));

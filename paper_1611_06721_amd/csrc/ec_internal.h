@@ -15,6 +15,7 @@ constexpr int kTile = 256;               // nodes per tile = threads per block
 constexpr int kMdBlocks = 256;           // grid of the basis-product kernels
 constexpr int kMdStride = 2 * kMaxWin;  // partial values per block
 constexpr int kMaxBlocks = 2048;        // grid cap of node kernels (multiple of 8)
+constexpr int kHaloMax = 256;           // one-tile iterations stage a halo of px <= this in LDS
 
 // Grid geometry and the constant-coefficient stencil of the nonconducting
 // region.  Every face touching a nonconducting edge lies between two

@@ -573,29 +573,48 @@ __device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, in
     // this block's tile (the map of for_tiles_b with one tile per block)
     const int tpx = (a.tiles + 7) >> 3, xcd = bid & 7, loc = bid >> 3;
     const int tile = xcd * tpx + loc;
-    const int n = tile * kTile + (int)threadIdx.x;
+    const int n0 = tile * kTile, tid = (int)threadIdx.x, n = n0 + tid;
     const bool valid = loc < tpx && tile < a.tiles && n < S;
     const int64_t bytes = 3 * S * (int64_t)sizeof(T);
     const __amdgpu_buffer_rsrc_t vr_b = buf_view(rc, bytes), vw_b = buf_view(wc, bytes),
                                  vs_b = buf_view(sp, bytes), vp_b = buf_view(a.p, bytes),
                                  vx_b = buf_view(a.x, bytes);
-    // stencil positions in the order of curlcurl_node: 8 of x, 8 of y, 8 of z
     const int oi = 1, oj = g.px, ok = g.px * g.py, Si = (int)S;
-    const int off[24] = {0, ok, -ok, ok - oi, -oi, oj, -oj, oj - oi,
-                         0, ok, -ok, -oj, ok - oj, oi, oi - oj, -oi,
-                         0, oj, oj - ok, -ok, -oj, oi, oi - ok, -oi};
-    T vr[24], vw[24], vs[24], op[3], ox[3];
+    // Positions of the 24-point stencil (order of curlcurl_node: 8 of x, 8
+    // of y, 8 of z).  The 15 in the node's own k-plane (offsets 0, +-1,
+    // +-px, +-(px - 1)) read t = D^-1 (r - alpha (w + beta s)) from an LDS
+    // copy of the tile and a halo of px nodes on each side; the 9 in the
+    // planes k +- 1 load r, w, s.  The node's own r, w, s (the centres) and
+    // the halo nodes' are loaded by the threads that write their t.
+    constexpr int kq[9] = {1, 2, 3, 9, 10, 12, 18, 19, 22};
+    const int koff[9] = {ok, -ok, ok - oi, ok, -ok, ok - oj, oj - ok, -ok, oi - ok};
+    T kr[9], kw[9], ks[9], cr[3], cw[3], cs[3], hr[2][3], hw[2][3], hs[2][3], op[3], ox[3];
 #pragma unroll
-    for (int q = 0; q < 24; ++q) {
-        const int e = (q >> 3) * Si + n + off[q];
-        vr[q] = buf_load<T>(vr_b, e);
-        vw[q] = buf_load<T>(vw_b, e);
-        vs[q] = FIRST ? (T)0 : buf_load<T>(vs_b, e);
+    for (int q = 0; q < 9; ++q) {
+        const int e = (kq[q] >> 3) * Si + n + koff[q];
+        kr[q] = buf_load<T>(vr_b, e);
+        kw[q] = buf_load<T>(vw_b, e);
+        ks[q] = FIRST ? (T)0 : buf_load<T>(vs_b, e);
     }
+    const bool halo = tid < oj;               // lanes that also load a left and a right halo node
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        op[c] = FIRST ? (T)0 : buf_load<T>(vp_b, c * Si + n);
-        ox[c] = buf_load<T>(vx_b, c * Si + n);
+        const int e = c * Si + n;
+        cr[c] = buf_load<T>(vr_b, e);
+        cw[c] = buf_load<T>(vw_b, e);
+        cs[c] = FIRST ? (T)0 : buf_load<T>(vs_b, e);
+        op[c] = FIRST ? (T)0 : buf_load<T>(vp_b, e);
+        ox[c] = buf_load<T>(vx_b, e);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            hr[h][c] = hw[h][c] = hs[h][c] = (T)0;
+            if (halo) {
+                const int eh = c * Si + (h == 0 ? n0 - oj + tid : n0 + kTile + tid);
+                hr[h][c] = buf_load<T>(vr_b, eh);
+                hw[h][c] = buf_load<T>(vw_b, eh);
+                hs[h][c] = FIRST ? (T)0 : buf_load<T>(vs_b, eh);
+            }
+        }
     }
     // the previous partials: every wave sums all of them itself (same order
     // in every wave: no barrier) and takes the decision in every lane (same
@@ -620,22 +639,35 @@ __device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, in
     if (c.done) return true;
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
     const T ta = (T)c.alpha, tb = (T)beta;
+    auto tf = [&](int comp, T r, T w, T s_) {
+        const T d = (T)dsel(dd, comp);
+        return FIRST ? d * (r - ta * w) : d * (r - ta * (w + tb * s_));
+    };
+    // t of the tile and its halo into LDS (slot of node m: m - n0 + px)
+    __shared__ T lt[3][kTile + 2 * kHaloMax];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lt[c][tid + oj] = tf(c, cr[c], cw[c], cs[c]);
+        if (halo) {
+            lt[c][tid] = tf(c, hr[0][c], hw[0][c], hs[0][c]);
+            lt[c][tid + oj + kTile] = tf(c, hr[1][c], hw[1][c], hs[1][c]);
+        }
+    }
+    __syncthreads();
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
         int i, j, k;
         decode(g, n, i, j, k);
-        T tv[24];
+        T tk[9];
 #pragma unroll
-        for (int q = 0; q < 24; ++q) {
-            const T d = (T)dsel(dd, q >> 3);
-            tv[q] = FIRST ? d * (vr[q] - ta * vw[q]) : d * (vr[q] - ta * (vw[q] + tb * vs[q]));
-        }
-        const T x0 = tv[0], x_kp = tv[1], x_km = tv[2], x_im_kp = tv[3], x_im = tv[4],
-                x_jp = tv[5], x_jm = tv[6], x_im_jp = tv[7];
-        const T y0 = tv[8], y_kp = tv[9], y_km = tv[10], y_jm = tv[11], y_jm_kp = tv[12],
-                y_ip = tv[13], y_ip_jm = tv[14], y_im = tv[15];
-        const T z0 = tv[16], z_jp = tv[17], z_jp_km = tv[18], z_km = tv[19], z_jm = tv[20],
-                z_ip = tv[21], z_ip_km = tv[22], z_im = tv[23];
+        for (int q = 0; q < 9; ++q) tk[q] = tf(kq[q] >> 3, kr[q], kw[q], ks[q]);
+        const int m = tid + oj;
+        const T x0 = lt[0][m], x_kp = tk[0], x_km = tk[1], x_im_kp = tk[2], x_im = lt[0][m - oi],
+                x_jp = lt[0][m + oj], x_jm = lt[0][m - oj], x_im_jp = lt[0][m + oj - oi];
+        const T y0 = lt[1][m], y_kp = tk[3], y_km = tk[4], y_jm = lt[1][m - oj], y_jm_kp = tk[5],
+                y_ip = lt[1][m + oi], y_ip_jm = lt[1][m + oi - oj], y_im = lt[1][m - oi];
+        const T z0 = lt[2][m], z_jp = lt[2][m + oj], z_jp_km = tk[6], z_km = tk[7],
+                z_jm = lt[2][m - oj], z_ip = lt[2][m + oi], z_ip_km = tk[8], z_im = lt[2][m - oi];
         const T Fx = y0 + z_jp - y_kp - z0;
         const T Fx_km = y_km + z_jp_km - y0 - z_km;
         const T Fx_jm = y_jm + z0 - y_jm_kp - z_jm;
@@ -653,8 +685,8 @@ __device__ __forceinline__ bool cg_iter_hoisted_t(const CgArgs<T> &a, int it, in
         for (int c = 0; c < 3; ++c) {
             const int64_t ix = c * S + n;
             const T d = (T)dsel(dd, c);
-            const T rv = vr[8 * c], wv = vw[8 * c];
-            const T si = FIRST ? wv : wv + tb * vs[8 * c];
+            const T rv = cr[c], wv = cw[c];
+            const T si = FIRST ? wv : wv + tb * cs[c];
             const T pi = FIRST ? d * rv : d * rv + tb * op[c];
             store_wt(a.x + ix, (T)(ox[c] + ta * pi));
             store_wt(a.p + ix, pi);
@@ -701,7 +733,7 @@ __device__ __forceinline__ bool cg_iter_hoisted(const CgArgs<T> &a, int it, int 
 template <typename T>
 __device__ __forceinline__ bool one_tile_per_block(const CgArgs<T> &a, int nb)
 {
-    return (nb >> 3) >= ((a.tiles + 7) >> 3);
+    return (nb >> 3) >= ((a.tiles + 7) >> 3) && a.g.px <= kHaloMax;
 }
 
 template <typename T>
@@ -1340,7 +1372,7 @@ hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st, bool
     // side inside a graph; co-residency holds because the grid fits the
     // device at once and stream order leaves it empty, and the bounded wait
     // of the barrier turns any violation into an error status
-    if ((blocks >> 3) >= ((a.tiles + 7) >> 3))
+    if ((blocks >> 3) >= ((a.tiles + 7) >> 3) && a.g.px <= kHaloMax)
         hipLaunchKernelGGL((k_cg_tail<T, true>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar,
                            fin ? 1 : 0);
     else
