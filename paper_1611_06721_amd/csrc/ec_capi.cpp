@@ -538,7 +538,9 @@ extern "C" int32_t ec_sizes(ec_handle h, int32_t window_cap, int64_t *n_padded, 
 // Shape of the 2.5D iteration.  Column width TI (x 256/TI nodes): least
 // idle threads, the widest on ties (contiguous rows along i beat a smaller
 // halo: 128^3 measured 151 us at 64x4 vs 168 us at 16x16); then the fewest
-// planes per block (>= 8) that keep the grid within kMaxBlocks.
+// planes per block (>= 16: the march fetches each plane one plane ahead, so
+// longer columns amortise its start; 128^3: 111 us at 16 planes) that keep
+// the grid within kMaxBlocks.
 // ti / kb > 0 force a shape.  Returns false when it does not fit (or, without
 // force, when the grid is too small to fill the chip with it).
 static bool plan_25(ec_problem *h, bool force, int ti_want = 0, int kb_want = 0)
@@ -559,7 +561,7 @@ static bool plan_25(ec_problem *h, bool force, int ti_want = 0, int kb_want = 0)
     }
     if (!bt) return false;
     const int tj = 256 / bt, nti = (nx + bt - 1) / bt, ntj = (ny + tj - 1) / tj;
-    int kb = kb_want > 0 ? std::min(kb_want, nz) : std::min(8, nz), ntk = 0;
+    int kb = kb_want > 0 ? std::min(kb_want, nz) : std::min(16, nz), ntk = 0;
     for (;; kb = std::min(nz, kb * 2)) {
         ntk = (nz + kb - 1) / kb;
         if (align_up((int64_t)nti * ntj * ntk, 8) <= kMaxBlocks || kb >= nz || kb_want > 0) break;
