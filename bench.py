@@ -39,14 +39,14 @@ METRIC = "Euler steps/sec at rel. residual 1e-8; PCG iters/step; SpMV HBM GB/s"
 BUDGET_MARGIN = 0
 # at most this many iteration kernels per captured solve on grids that run the
 # node-parallel iteration; a longer solve continues in the persistent tail
-# (an iteration there costs about 7 us more than a launched one at 48^3, a
-# launch that finds the solve finished about 4.5 us), so a short warm-up
-# (whose last steps still need many iterations: the window is not yet full)
-# cannot make every replay issue dozens of kernels that find the solve
-# finished.  48^3, SPE: caps of 6/9/12/16/20/24 gave 1757/1849/1899/1931/
-# 1961/1975 steps/s over steps 6-25 (after 5 warm-up steps, 20.3 PCG
-# iterations per step) and 3320/3373/3353/3331/3339/3338 over steps 41-240
-# (warm-up median 13, 6.5 iterations per step)
+# (an iteration there costs about 1.5 us more than a launched one at 48^3, a
+# launch that finds the solve finished 1-2 us), so a short warm-up (whose
+# last steps still need many iterations: the window is not yet full) cannot
+# make every replay issue dozens of kernels that find the solve finished.
+# 48^3, SPE: caps of 12/16/20/24/28/32/40 gave 2275/2417/2441/2440/2419/
+# 2353/2215 steps/s over steps 6-25 (after 5 warm-up steps, 20.3 PCG
+# iterations per step) and 3938/3896/3896/3899/3899/3896/3889 over steps
+# 41-240 (warm-up median 13, 6.15 iterations per step)
 BUDGET_CAP_NODE = 24
 
 
