@@ -1071,6 +1071,9 @@ static int32_t run_cg64(ec_problem *h, int seq, int mode, const double *b, const
                         double *x, const ec_solve_opts *o, ec_solve_info *info)
 {
     CgArgs<double> a = cg64_args(h, seq, b, bscale, x, o, info);
+    // an SPE/POD start: its combination's residual sums (h->part_md) let the
+    // init kernel stop a solve the start already solved
+    if (mode == START_DEV) a.start_part = h->part_md;
     cg64_init(h, a, mode);
     int issued = 0;
     bool fin_done = false;
@@ -2725,6 +2728,9 @@ static int32_t batch_tables(ec_batch_s *b, const ec_step_opts *so, const double 
                                                       h->sj, o, nullptr));
             else b->tab[s].push_back(cg64_args(h, EC_SEQ_CPL, h->bcpl, nullptr, h->sc, o, nullptr));
             if (!basis) continue;
+            // the instance's start combination writes its residual sums here
+            // (its pushes run after the solve's init)
+            b->tab[s].back().start_part = h->part_md;
             seq_ensure(h, seq, meth, so->window, so->pod_kmax, so->pod_eps);
             seq_eta_ensure(h, seq, meth, spe_eta(h, o->precision));
             const CgArgs<double> &a = b->tab[s].back();

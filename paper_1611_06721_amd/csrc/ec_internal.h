@@ -189,6 +189,10 @@ struct CgArgs {
     int seq_id;
     int accum;               // add iterations to info->iters (inner refinement solves)
     const int *skip;         // device flag: nonzero -> kernels return at once
+    // partials of the start combination that wrote x0 and r0 (value-major
+    // rows |x0|^2, |r0|^2, |b|^2 over kMdBlocks blocks), or nullptr: the init
+    // kernel stops a solve whose start already meets the tolerance
+    const double *start_part;
     int tiles;
     int blocks;
     unsigned *bar;           // grid-barrier words of the tail kernel (kBarWords x kBarStride)

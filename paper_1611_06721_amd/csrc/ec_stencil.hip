@@ -284,6 +284,34 @@ __device__ __forceinline__ void cg_init_body(const CgArgs<T> &a, int mode, int b
     const double dd[3] = {g.dinv[0], g.dinv[1], g.dinv[2]};
     const double bs = a.bscale ? *a.bscale : 1.0;
     if (mode == START_DEV) mode = a.seq->zero_start ? START_ZERO : START_R;
+    if (mode == START_R && a.start_part) {
+        // the start combination's own sums of r0^2 and b^2: a start vector
+        // that already meets the tolerance (the test of the first
+        // iteration's decision) ends the solve here, with no stencil pass;
+        // the iteration kernels then find the record finished
+        __shared__ double s_v[3];
+        reduce_rows<3>(a.start_part, 3, 3, s_v);
+        const double rr = s_v[1], bb = s_v[2];
+        const double rtol = a.rtol_dev ? *a.rtol_dev : a.rtol;
+        const double tol2 = rtol * rtol * bb;
+        if (rr == rr && rr <= 1e300 && (bb == 0.0 || rr <= tol2)) {
+            if (bid == 0 && threadIdx.x == 0) {
+                CgCtl c0{};
+                c0.done = 1;
+                c0.status = EC_OK;
+                c0.bb = bb;
+                c0.tol2 = tol2;
+                c0.rho0 = rr;
+                c0.rho = rr;
+                c0.it = 0;
+                a.ctl[0] = c0;
+            }
+            if (bid == 0 && a.bar)
+                for (int q = threadIdx.x; q < kBarWords; q += blockDim.x)
+                    a.bar[(int64_t)q * kBarStride] = 0u;
+            return;
+        }
+    }
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     T *r0 = a.rb[0];
     double *P0 = a.part, *P1 = a.part + 4 * (int64_t)kMaxBlocks;
