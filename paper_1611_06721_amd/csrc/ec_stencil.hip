@@ -997,13 +997,16 @@ __global__ void __launch_bounds__(256)
         fetch(k0 + 1, po, ph);
         const T wx = (T)g.wx, wy = (T)g.wy, wz = (T)g.wz;
         for (int k = k0; k < k1; ++k) {
-            // the node's p of plane k first: its loads overlap those of
-            // plane k + 2 (neither waits for the barrier)
+            // the node's p and x of plane k first: their loads overlap those
+            // of plane k + 2 (neither waits for the barrier)
             const int64_t n = k * ok + (int64_t)j * oj + i;
-            T opv[3] = {(T)0, (T)0, (T)0};
-            if (own && !first) {
+            T opv[3] = {(T)0, (T)0, (T)0}, oxv[3] = {(T)0, (T)0, (T)0};
+            if (own) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) opv[c] = a.p[c * S + n];
+                for (int c = 0; c < 3; ++c) {
+                    if (!first) opv[c] = a.p[c * S + n];
+                    oxv[c] = a.x[c * S + n];
+                }
             }
             store_plane(k + 1, po, ph, nr, nu);
             if (k + 2 <= k1) fetch(k + 2, po, ph);
@@ -1040,7 +1043,7 @@ __global__ void __launch_bounds__(256)
                     const T d = dd[c];
                     const T rv = cr[c], si = cu[c];
                     const T pi = first ? d * rv : d * rv + tb * opv[c];
-                    st25(a.x + ix, (T)(a.x[ix] + ta * pi));
+                    st25(a.x + ix, (T)(oxv[c] + ta * pi));
                     st25(a.p + ix, pi);
                     st25(sc + ix, si);
                     const T r1 = rv - ta * si;
