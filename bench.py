@@ -76,15 +76,33 @@ def method_opts(ec, name, rtol, graph_iters=(0, 0)):
     return ec.step_opts(ec.SV_ZERO, window=1, **kw)
 
 
+def graph_budgets(its, warmup, cap=None):
+    """Iteration kernels per captured solve (source, coupling) from the
+    per-solve iteration counts of the eager warm-up (its: source and coupling
+    counts of each step, interleaved).  Typical, not worst-case, counts: the
+    median over the last min(W/2, W-2) warm-up steps (never the first step
+    from rest while W > 2); a longer solve is finished by the persistent tail
+    kernel.  A sequence that needs no iteration (the source solves once their
+    window holds the source shape) gets two: an iteration kernel, then a tail
+    launch, both of which find the solve finished.  At most `cap` each."""
+    import numpy as np
+    its = np.asarray(its)
+    h = min(warmup // 2, max(warmup - 2, 0))
+    med = [int(np.median(its[2 * h + q::2])) for q in (0, 1)]
+    budgets = [max(1, v + BUDGET_MARGIN) if v > 0 else 2 for v in med]
+    if cap:
+        budgets = [min(b, cap) for b in budgets]
+    return budgets
+
+
 def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None, cap=None):
     """`warmup` eager steps from rest (not timed; they also fill the start-vector
     histories), then `steps` replays of the captured step, continuing the same
     run, timed with events on the library's stream.  Each captured solve issues
-    a fixed number of PCG iteration kernels, sized from the second half of the
-    warm-up and capped at `cap` (None: no cap); a solve that needs more
-    continues in one persistent launch.  If a solve still fails (maxit), the
-    measurement is repeated with twice the budget."""
-    import numpy as np
+    a fixed number of PCG iteration kernels (`graph_budgets`: the last warm-up
+    steps, capped at `cap`); a solve that needs more continues in one
+    persistent launch.  If a solve still fails (maxit), the measurement is
+    repeated with twice the budget."""
     if make_opts is None:
         def make_opts(graph_iters=(0, 0)):
             return method_opts(ec, name, rtol, graph_iters)
@@ -96,20 +114,7 @@ def run_method(ec, torch, G, name, dt, steps, warmup, rtol, make_opts=None, cap=
         G.run(A, 0, warmup, dt, make_opts(), info=info)
         its = ec.info_array(info)["iters"]
         if budgets is None:
-            # typical, not worst-case, counts (the median of the second half
-            # of the warm-up): a longer solve is finished by the persistent
-            # tail kernel, whose iterations cost little more than launches;
-            # a sequence that needs no iteration (the source solves once
-            # their window holds the source shape) gets a budget of two: the
-            # deciding iteration as an ordinary kernel, then a tail launch
-            # that finds the solve finished (a budget of one, the tail
-            # deciding, measured about 1 % slower: the tail's blocks hold a
-            # CU's registers while the other branch's pushes run)
-            h = min(warmup // 2, max(warmup - 2, 0))
-            med = [int(np.median(its[2 * h + q::2])) for q in (0, 1)]
-            budgets = [max(1, v + BUDGET_MARGIN) if v > 0 else 2 for v in med]
-            if cap:
-                budgets = [min(b, cap) for b in budgets]
+            budgets = graph_budgets(its, warmup, cap)
         G.counters_reset()
         graph = G.graph_capture(A, dt, make_opts(tuple(budgets)))
         torch.cuda.synchronize()
