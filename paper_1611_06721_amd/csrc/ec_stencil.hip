@@ -1441,9 +1441,13 @@ template <typename T>
 hipError_t cg_tail(const CgArgs<T> &a, int it0, int blocks, hipStream_t st, bool fin)
 {
     // a plain launch: a cooperative one costs ~11 us of idle device on each
-    // side inside a graph; co-residency holds because the grid fits the
-    // device at once and stream order leaves it empty, and the bounded wait
-    // of the barrier turns any violation into an error status
+    // side inside a graph.  The grid (two blocks per CU at most) fits the
+    // device at once.  Kernels of another stream (the history pushes that a
+    // captured step forks) may hold CUs while it starts: they do not wait
+    // for the tail, so they finish and its remaining blocks then start, the
+    // early ones waiting at the barrier meanwhile (the pushes' blocks still
+    // fit beside two tail blocks per CU); the bounded wait of the barrier
+    // turns any violation into an error status
     if ((blocks >> 3) >= ((a.tiles + 7) >> 3) && a.g.px <= kHaloMax)
         hipLaunchKernelGGL((k_cg_tail<T, true>), dim3(blocks), dim3(kTile), 0, st, a, it0, a.bar,
                            fin ? 1 : 0);

@@ -424,6 +424,44 @@ def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
     assert c["iters_cpl"] == 5
 
 
+def test_graph_forked_starved_48(ec):
+    """The benchmark's 48^3 Brauer grid and step shape (SPE m = 8, rtol 1e-8),
+    captured with the history pushes on the forked side stream and budgets far
+    too small (one source and two coupling iteration kernels): the persistent
+    tail runs beside the pushes of the other sequence, which hold CUs while
+    its blocks arrive at the grid barrier; the replays must still be bitwise
+    the eager steps, with no error record."""
+    import torch
+    wl = synth.nonlinear(48)
+    opts = ec.step_opts(ec.SV_SPE, window=8, pod_kmax=8, rtol=1e-8)
+    G1 = ec.Problem(wl, window_cap=8)
+    dt = 0.5 * 2.0 / G1.cfl(iters=60, rtol=1e-10)
+    A1 = G1.zeros()
+    G1.set_state(A1, rtol=1e-8)
+    info1 = G1.info(2 * 20)
+    G1.run(A1, 0, 20, dt, opts, info=info1)
+    its = ec.info_array(info1)["iters"]
+    ref = A1.cpu().numpy()
+    G1.close()
+    G2 = ec.Problem(wl, window_cap=8)
+    A2 = G2.zeros()
+    G2.set_state(A2, rtol=1e-8)
+    G2.run(A2, 0, 5, dt, opts)
+    G2.counters_reset()
+    g = G2.graph_capture(A2, dt, ec.step_opts(ec.SV_SPE, window=8, pod_kmax=8, rtol=1e-8,
+                                              graph_iters=(1, 2), graph_serial=False))
+    for _ in range(15):
+        g.launch()
+    torch.cuda.synchronize()
+    c = G2.counters()
+    assert c["worst_status"] == 0 and c["steps"] == 15
+    assert c["iters_src"] + c["iters_cpl"] == int(its[10:].sum())
+    assert int(its[11::2].max()) > 2        # the tail carried coupling iterations
+    assert np.array_equal(A2.cpu().numpy(), ref)
+    g.close()
+    G2.close()
+
+
 def test_step_info_records(ec, oracle_mod):
     G, O, _ = pair(ec, oracle_mod, "c1")
     dt = 0.9 * 2 / O.power(iters=40)
