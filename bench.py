@@ -39,15 +39,23 @@ METRIC = "Euler steps/sec at rel. residual 1e-8; PCG iters/step; SpMV HBM GB/s"
 BUDGET_MARGIN = 0
 # at most this many iteration kernels per captured solve on grids that run the
 # node-parallel iteration; a longer solve continues in the persistent tail
-# (an iteration there costs about 1.5 us more than a launched one at 48^3, a
-# launch that finds the solve finished 1-2 us), so a short warm-up (whose
-# last steps still need many iterations: the window is not yet full) cannot
-# make every replay issue dozens of kernels that find the solve finished.
-# 48^3, SPE: caps of 12/16/20/24/28/32/40 gave 2275/2417/2441/2440/2419/
-# 2353/2215 steps/s over steps 6-25 (after 5 warm-up steps, 20.3 PCG
-# iterations per step) and 3938/3896/3896/3899/3899/3896/3889 over steps
+# (an iteration there costs about 3 us more than a launched one at 48^3, a
+# launch that finds the solve finished 1-2 us), so a short warm-up whose last
+# steps still need many iterations (an SPE window that is not yet full)
+# cannot make every replay issue dozens of kernels that find the solve
+# finished.  48^3, SPE: caps of 12/16/20/24/28/32/40 gave 2275/2417/2441/
+# 2440/2419/2353/2215 steps/s over steps 6-25 (after 5 warm-up steps, 20.3
+# PCG iterations per step) and 3938/3896/3896/3899/3899/3896/3889 over steps
 # 41-240 (warm-up median 13, 6.15 iterations per step)
 BUDGET_CAP_NODE = 24
+# The cap per start method: only the SPE windows shrink their solves' needs
+# after a short warm-up; the other methods need about as many iterations in
+# the timed steps as in the last warm-up ones, and a cap would only move
+# their iterations into the slower tail.  Steps 6-25 at 48^3, caps 24/48/96/
+# none: POD 817/880/921/919 steps/s, PREV 304/322/366/406, ZERO 273/288/323/
+# 361, the growing SPE basis 2469/2082/1685/1682.
+METHOD_BUDGET_CAP = {"spe": BUDGET_CAP_NODE, "cspe": BUDGET_CAP_NODE, "pod": None,
+                     "prev": None, "zero": None}
 
 
 def log(*a):
@@ -689,7 +697,7 @@ def main():
     for name in args.methods.split(","):
         log(f"[bench] method {name}: warmup {args.warmup}, {args.steps} steps")
         r, _ = run_method(ec, torch, G, name, dt, args.steps, args.warmup, rtol,
-                          cap=BUDGET_CAP_NODE)
+                          cap=METHOD_BUDGET_CAP.get(name))
         results[name] = r
         log(f"[bench] {name}: {r['steps_per_s']:.1f} steps/s, {r['iters_per_step']:.2f} iters/step")
     head = "spe" if "spe" in results else next(iter(results))

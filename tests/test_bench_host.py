@@ -62,3 +62,14 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "--gpus 1" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_budget_cap_per_method():
+    """Every start method the bench runs has a cap entry; only the SPE
+    windows (whose needs fall once the window fills) are capped."""
+    import bench
+    for name in ("spe", "cspe", "pod", "prev", "zero"):
+        assert name in bench.METHOD_BUDGET_CAP
+    assert bench.METHOD_BUDGET_CAP["spe"] == bench.BUDGET_CAP_NODE
+    assert bench.METHOD_BUDGET_CAP["cspe"] == bench.BUDGET_CAP_NODE
+    assert all(bench.METHOD_BUDGET_CAP[m] is None for m in ("pod", "prev", "zero"))
