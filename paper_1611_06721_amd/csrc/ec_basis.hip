@@ -287,12 +287,17 @@ __device__ __forceinline__ void chol_store(SeqDev *sq)
 // with the first one that rotates nothing (a test on the whole off-diagonal
 // mass against 1e-30 of the diagonal's rarely passed once rounding noise
 // dominated it, so most calls ran the sweep limit; a purely relative
-// threshold never passes on such a matrix).
-__device__ void jacobi_eig(double *A, double *V, int n)
+// threshold never passes on such a matrix).  A round applies its rotations
+// from both sides in one pass, J^T A J element by element (the column
+// rotation first, then the row rotation, as two passes would), from A into
+// the scratch B and back on the next round, with V J in the same pass: one
+// barrier after the rotation angles, one after the update, none for a round
+// that rotates nothing.  B is scratch of the same shape as A.
+__device__ void jacobi_eig(double *A, double *B, double *V, int n)
 {
-    __shared__ double cs[K / 2 + 1][2];
-    __shared__ int pr[K / 2 + 1][2];
-    __shared__ int s_rot;
+    __shared__ double cs[K][2];          // rotation of the pair that index i belongs to
+    __shared__ int mate[K], role[K];     // its partner and whether i is the pair's p (0) or q (1)
+    __shared__ int s_rot, s_any[K];
     __shared__ double s_tr;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int m = (n + 1) & ~1;
@@ -303,61 +308,87 @@ __device__ void jacobi_eig(double *A, double *V, int n)
     }
     __syncthreads();
     const double floor_abs = 1e-15 * s_tr;
+    double *cur = A, *nxt = B;
     for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) s_rot = 0;
+        if (tid == 0) {
+            s_rot = 0;
+            for (int r = 0; r < m - 1; ++r) s_any[r] = 0;
+        }
         __syncthreads();
         for (int round = 0; round < m - 1; ++round) {
             if (tid < m / 2) {
-                auto slot = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + round) % (m - 1); };
+                auto slot = [&](int sl) { return sl == 0 ? 0 : 1 + (sl - 1 + round) % (m - 1); };
                 int p = slot(tid), q = slot(m - 1 - tid);
                 if (p > q) { const int t = p; p = q; q = t; }
-                pr[tid][0] = p;
-                pr[tid][1] = q;
-                double c = 1.0, s = 0.0;
+                double c = 1.0, sn = 0.0;
                 if (q < n) {
-                    const double apq = A[p * K + q];
+                    const double apq = cur[p * K + q];
                     const double thr =
-                        1e-14 * sqrt(fabs(A[p * K + p] * A[q * K + q])) + floor_abs;
+                        1e-14 * sqrt(fabs(cur[p * K + p] * cur[q * K + q])) + floor_abs;
                     if (fabs(apq) > thr) {
                         s_rot = 1;
-                        const double th = (A[q * K + q] - A[p * K + p]) / (2.0 * apq);
+                        s_any[round] = 1;
+                        const double th = (cur[q * K + q] - cur[p * K + p]) / (2.0 * apq);
                         const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
+                        sn = t * c;
                     }
+                    cs[p][0] = c; cs[p][1] = sn; mate[p] = q; role[p] = 0;
+                    cs[q][0] = c; cs[q][1] = sn; mate[q] = p; role[q] = 1;
+                } else if (p < n) {
+                    cs[p][0] = 1.0; cs[p][1] = 0.0; mate[p] = p; role[p] = 0;
                 }
-                cs[tid][0] = c;
-                cs[tid][1] = s;
             }
             __syncthreads();
-            for (int t = tid; t < (m / 2) * n; t += nt) {       // A <- A J, V <- V J
-                const int pi = t / n, r = t - pi * n;
-                const int p = pr[pi][0], q = pr[pi][1];
-                if (q >= n) continue;
-                const double c = cs[pi][0], s = cs[pi][1];
-                const double ap = A[r * K + p], aq = A[r * K + q];
-                A[r * K + p] = c * ap - s * aq;
-                A[r * K + q] = s * ap + c * aq;
-                const double vp = V[r * K + p], vq = V[r * K + q];
-                V[r * K + p] = c * vp - s * vq;
-                V[r * K + q] = s * vp + c * vq;
+            if (!s_any[round]) continue;          // uniform: nothing to rotate
+            for (int t = tid; t < n * K; t += nt) {            // K: a constant divisor
+                const int i = t / K, jj = t - i * K;
+                if (jj >= n) continue;
+                // column rotation of rows i and its mate at column jj, then the
+                // row rotation of the pair of i
+                const int pi = role[i] ? mate[i] : i, qi = role[i] ? i : mate[i];
+                const int pj = role[jj] ? mate[jj] : jj, qj = role[jj] ? jj : mate[jj];
+                const double cj = cs[jj][0], sj = cs[jj][1], ci = cs[i][0], si = cs[i][1];
+                double col_p, col_q;       // (A J)[pi][jj], (A J)[qi][jj]
+                if (pj == qj) {
+                    col_p = cur[pi * K + jj];
+                    col_q = cur[qi * K + jj];
+                } else if (role[jj] == 0) {
+                    col_p = cj * cur[pi * K + pj] - sj * cur[pi * K + qj];
+                    col_q = cj * cur[qi * K + pj] - sj * cur[qi * K + qj];
+                } else {
+                    col_p = sj * cur[pi * K + pj] + cj * cur[pi * K + qj];
+                    col_q = sj * cur[qi * K + pj] + cj * cur[qi * K + qj];
+                }
+                double v;
+                if (pi == qi) v = col_p;
+                else if (role[i] == 0) v = ci * col_p - si * col_q;
+                else v = si * col_p + ci * col_q;
+                nxt[i * K + jj] = v;
+            }
+            for (int t = tid; t < n * K; t += nt) {       // V <- V J (pairs of columns)
+                const int r = t / K, jj = t - r * K;
+                if (jj >= n || role[jj] != 0 || mate[jj] == jj) continue;
+                const int q = mate[jj];
+                const double c = cs[jj][0], sn = cs[jj][1];
+                const double vp = V[r * K + jj], vq = V[r * K + q];
+                V[r * K + jj] = c * vp - sn * vq;
+                V[r * K + q] = sn * vp + c * vq;
             }
             __syncthreads();
-            for (int t = tid; t < (m / 2) * n; t += nt) {       // A <- J^T A
-                const int pi = t / n, cc = t - pi * n;
-                const int p = pr[pi][0], q = pr[pi][1];
-                if (q >= n) continue;
-                const double c = cs[pi][0], s = cs[pi][1];
-                const double ap = A[p * K + cc], aq = A[q * K + cc];
-                A[p * K + cc] = c * ap - s * aq;
-                A[q * K + cc] = s * ap + c * aq;
-            }
-            __syncthreads();
+            double *t2 = cur; cur = nxt; nxt = t2;
         }
         // every thread reads the flag before thread 0 clears it again
         const int rotated = s_rot;
         __syncthreads();
         if (!rotated) break;
+    }
+    if (cur != A) {
+        for (int t = tid; t < n * n; t += nt) {
+            const int i = t / n, jj = t - i * n;
+            A[i * K + jj] = cur[i * K + jj];
+        }
+        __syncthreads();
     }
 }
 
@@ -581,14 +612,22 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
             Ms[i * K + j] = s;
         }
         __syncthreads();
-        jacobi_eig(Ms, Vs, n);
+        jacobi_eig(Ms, Ls, Vs, n);
+        // descending order of the eigenvalues (ties by index, a NaN below
+        // every number, so that the ranks stay a permutation): thread i puts
+        // i at its rank
+        if (tid < n) {
+            auto key = [](double v) { return v == v ? v : -INFINITY; };
+            const double li = key(Ms[tid * K + tid]);
+            int r = 0;
+            for (int j = 0; j < n; ++j) {
+                const double lj = key(Ms[j * K + j]);
+                r += (lj > li || (lj == li && j < tid)) ? 1 : 0;
+            }
+            ord[r] = tid;
+        }
+        __syncthreads();
         if (tid == 0) {
-            for (int i = 0; i < n; ++i) ord[i] = i;
-            for (int i = 0; i < n; ++i)
-                for (int j = i + 1; j < n; ++j)
-                    if (Ms[ord[j] * K + ord[j]] > Ms[ord[i] * K + ord[i]]) {
-                        const int t = ord[i]; ord[i] = ord[j]; ord[j] = t;
-                    }
             double tot = 0.0;
             for (int i = 0; i < n; ++i) {
                 const double l = Ms[ord[i] * K + ord[i]];
@@ -611,23 +650,28 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
             sq->V[t] = (i < n && j < n) ? Vs[i * K + ord[j]] : (i == j ? 1.0 : 0.0);
         }
         __syncthreads();
+        // the sorted eigenvectors are Vs[., ord[.]] (the copy in sq->V above
+        // is for the next call's warm start)
         const int kp = sq->kpod;
         for (int t = tid; t < n * kp; t += nt) {               // Ls = H V_k
             const int l = t / kp, b2 = t - l * kp;
+            const int ob = ord[b2];
             double h = 0.0;
-            for (int m2 = 0; m2 < n; ++m2) h += sq->H[l * K + m2] * sq->V[m2 * K + b2];
+            for (int m2 = 0; m2 < n; ++m2) h += sq->H[l * K + m2] * Vs[m2 * K + ob];
             Ls[l * K + b2] = h;
         }
         __syncthreads();
         for (int t = tid; t < kp * kp; t += nt) {              // Sigma^-1 V_k^T H V_k Sigma^-1
             const int a2 = t / kp, b2 = t - a2 * kp;
+            const int oa = ord[a2];
             double h = 0.0;
-            for (int l = 0; l < n; ++l) h += sq->V[l * K + a2] * Ls[l * K + b2];
+            for (int l = 0; l < n; ++l) h += Vs[l * K + oa] * Ls[l * K + b2];
             Ms[a2 * K + b2] = h / (sg[a2] * sg[b2]);
         }
         for (int a2 = tid; a2 < kp; a2 += nt) {                // Sigma^-1 V_k^T X^T b
+            const int oa = ord[a2];
             double s = 0.0;
-            for (int l = 0; l < n; ++l) s += sq->V[l * K + a2] * val[l];
+            for (int l = 0; l < n; ++l) s += Vs[l * K + oa] * val[l];
             gs[a2] = s / sg[a2];
         }
         __syncthreads();
@@ -638,7 +682,7 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
             for (int l = 0; l < K; ++l) {
                 double z = 0.0;
                 if (good && l < n)
-                    for (int j = 0; j < kp; ++j) z += sq->V[l * K + j] * ys[j] / sg[j];
+                    for (int j = 0; j < kp; ++j) z += Vs[l * K + ord[j]] * ys[j] / sg[j];
                 sq->cA[l] = z;
                 sq->cB[l] = -z;
             }
