@@ -392,10 +392,93 @@ __device__ void jacobi_eig(double *A, double *B, double *V, int n)
     }
 }
 
+// The sequence state that the SPE start's dense step reads, requested by
+// the whole block before the partial rows are reduced (one round trip
+// alongside theirs instead of a chain of dependent loads): the column
+// scales, the stored factor of H and whether it is current.
+struct SpePre {
+    double L[K * K];
+    double s[K + 1];
+    int use, bad;
+};
+
+// Range-checked raw buffer view of `bytes` bytes at p: a load at byte
+// offset o reads memory only when 0 <= o < bytes and returns 0 otherwise,
+// with no branch (so that the loads of one step go out together).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t seq_view(const void *p, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+
+__device__ __forceinline__ double view_f64(__amdgpu_buffer_rsrc_t r, int e)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0));
+}
+
+// The SPE start's inputs in registers of a 256-thread block: up to three
+// factor entries and one scale per thread, the factor's currency words and
+// the window size, all requested before any of them is used.
+struct SpePreRegs {
+    double l[(K * K + 255) / 256];
+    double sc;
+    int use, bad, k;
+};
+
+__device__ __forceinline__ void spe_pre_issue(const SeqDev *sq, SpePreRegs &r)
+{
+    const int tid = threadIdx.x;
+    const __amdgpu_buffer_rsrc_t vl = seq_view(sq->L, K * K * 8), vs = seq_view(sq->s, (K + 1) * 8);
+#pragma unroll
+    for (int u = 0; u < (K * K + 255) / 256; ++u) r.l[u] = view_f64(vl, tid + 256 * u);
+    r.sc = view_f64(vs, tid);
+    r.use = sq->L_ver == sq->H_ver;
+    r.bad = sq->chol_bad;
+    r.k = sq->k;
+}
+
+__device__ __forceinline__ void spe_pre_commit(const SpePreRegs &r, SpePre *pre)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < (K * K + 255) / 256; ++u) {
+        const int t = tid + 256 * u;
+        if (t < K * K) pre->L[t] = r.l[u];
+    }
+    if (tid < K + 1) pre->s[tid] = r.sc;
+    if (tid == 0) {
+        pre->use = r.use;
+        pre->bad = r.bad;
+    }
+}
+
+// chol_solve_stored on the preloaded factor: the same substitutions on
+// thread 0, in the same order, on the same values.
+__device__ __forceinline__ bool chol_solve_pre(const SpePre *pre, double *y, const double *gv,
+                                               int n, bool *good)
+{
+    if (!(n <= kCholReg && pre->use)) return false;
+    if (threadIdx.x == 0) {
+        const double *L = pre->L;
+        for (int i = 0; i < n; ++i) {
+            double t = gv[i];
+            for (int j = 0; j < i; ++j) t -= L[i * K + j] * y[j];
+            y[i] = t / L[i * K + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int j = i + 1; j < n; ++j) t -= L[j * K + i] * y[j];
+            y[i] = t / L[i * K + i];
+        }
+    }
+    __syncthreads();
+    *good = pre->bad == 0;
+    return true;
+}
+
 // ------------------------------------------------------- dense steps
 // val: the reduced values of the preceding basis product (see OP_* codes).
 __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, double tol,
-                                         ec_solve_info *info)
+                                         ec_solve_info *info, const SpePre *pre = nullptr)
 {
     __shared__ double Ms[K * K], Ls[K * K], Vs[K * K];
     __shared__ double ys[K + 1], gs[K + 1], sg[K + 1];
@@ -406,15 +489,17 @@ __device__ __forceinline__ void small_op(SeqDev *sq, int op, const double *val, 
     switch (op) {
     case OP_SPE_START: {
         // g = q^T b, H y = g, x0 = q y, r0 = b - K q y
-        for (int i = tid; i < k; i += nt) gs[i] = sq->s[i] * val[i];
+        const double *sc = pre ? pre->s : sq->s;
+        for (int i = tid; i < k; i += nt) gs[i] = sc[i] * val[i];
         __syncthreads();
         bool good = k > 0;
-        if (good && !chol_solve_stored(sq, Ls, ys, gs, k, &good))
+        if (good && !(pre ? chol_solve_pre(pre, ys, gs, k, &good)
+                          : chol_solve_stored(sq, Ls, ys, gs, k, &good)))
             good = chol_solve(sq->H, Ls, ys, gs, k, sq->hscale);
         // entries are independent: one per thread (no chain of dependent
         // global loads and stores on thread 0)
         for (int i = tid; i < K; i += nt) {
-            const double c = (good && i < k) ? ys[i] * sq->s[i] : 0.0;
+            const double c = (good && i < k) ? ys[i] * sc[i] : 0.0;
             sq->cA[i] = c;
             sq->cB[i] = -c;
         }
@@ -1118,6 +1203,34 @@ __device__ __forceinline__ void small_body(const SmallArgs &sa)
     default: break;
     }
     nv = nv < 0 ? 0 : (nv > nvals ? nvals : nv);
+    if constexpr (OP == OP_SPE_START) {
+        // reduce_rows with every load (the sequence state and all nvals
+        // partial rows) issued before the first is used: the same wave
+        // butterflies and the same four-wave sum, so the same values
+        __shared__ SpePre pre;
+        __shared__ double tmp[NV][4];
+        SpePreRegs pr;
+        spe_pre_issue(sq, pr);
+        const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+        double rv[NV];
+        const __amdgpu_buffer_rsrc_t vp = seq_view(part, part ? nvals * kMdBlocks * 8 : 0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) rv[q] = view_f64(vp, q * kMdBlocks + tid);
+        const int kk = pr.k < 0 ? 0 : (pr.k > nvals ? nvals : pr.k);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            if (q < kk) {
+                const double sm = wave_sum(rv[q]);
+                if (lane == 0) tmp[q][wv] = sm;
+            }
+        }
+        spe_pre_commit(pr, &pre);
+        __syncthreads();
+        if (tid < kk) val[tid] = ((tmp[tid][0] + tmp[tid][1]) + tmp[tid][2]) + tmp[tid][3];
+        __syncthreads();
+        small_op(sq, op, val, sa.tol, sa.info, &pre);
+        return;
+    }
     if (part) reduce_rows<NV>(part, nvals, nv, val);
     __syncthreads();
     small_op(sq, op, val, sa.tol, sa.info);
