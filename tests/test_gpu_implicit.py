@@ -2,6 +2,8 @@
 Newton on the Schur form, GMRES on J = M_c/dt + J_N - S with K_n^+ inside
 every product) against the oracle (oracle/implicit.py, pinned by the dense
 Schur solve, closed-form decay and quadratic convergence)."""
+import time
+
 import numpy as np
 import pytest
 
@@ -74,15 +76,30 @@ def test_implicit_eigenmode_decay(ec, oracle_mod):
     G.close()
 
 
+_NONLIN = {}
+
+
+def _nonlinear_reference(oracle_mod):
+    """The oracle's eight Newton steps (CPU, a few seconds), made once for
+    both start methods."""
+    if not _NONLIN:
+        from oracle import implicit
+        wl = synth.nonlinear(16, ramp_steps=8, J0=6.0e6)
+        P = oracle_mod.Problem(wl)
+        dt = 10 * 2 / P.power(iters=60)
+        t0 = time.time()
+        Ao, its = implicit.run(P, dt, 8, tol=1e-12)
+        print(f"oracle implicit nl16: {time.time() - t0:.1f} s, newton {its}", flush=True)
+        _NONLIN.update(wl=wl, P=P, dt=dt, Ao=Ao, its=its)
+    return _NONLIN
+
+
 @pytest.mark.parametrize("method", [0, 2])
 def test_implicit_nonlinear_trajectory(ec, oracle_mod, method):
     """Brauer iron driven into saturation, dt ten times the explicit bound:
     eight implicit steps against the oracle's (Newton to 1e-12)."""
-    from oracle import implicit
-    wl = synth.nonlinear(16, ramp_steps=8, J0=6.0e6)
-    P = oracle_mod.Problem(wl)
-    dt = 10 * 2 / P.power(iters=60)
-    Ao, its = implicit.run(P, dt, 8, tol=1e-12)
+    ref = _nonlinear_reference(oracle_mod)
+    wl, P, dt, Ao, its = ref["wl"], ref["P"], ref["dt"], ref["Ao"], ref["its"]
     B = P.cell_B(Ao)[wl.cell_mat.astype(bool)]
     G = ec.Problem(wl, window_cap=8)
     A = G.zeros()
@@ -93,7 +110,9 @@ def test_implicit_nonlinear_trajectory(ec, oracle_mod, method):
     # conditioning (about 1e-12 relative here); Newton stops at 1e-10
     kw = dict(TIGHT, newton_rtol=1e-10) if method == ec.SV_SPE else TIGHT
     for m in range(1, 9):
+        t0 = time.time()
         r = G.implicit_step(A, m, dt, method=method, **kw)
+        print(f"implicit step {m} (method {method}): {time.time() - t0:.2f} s, {r}", flush=True)
         assert r["status"] == 0, r
         nits.append(r["newton_iters"])
     got = A.cpu().numpy()
