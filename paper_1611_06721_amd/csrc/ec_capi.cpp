@@ -3,6 +3,7 @@
 // start vectors and explicit Euler steps.  All arithmetic on edge arrays runs
 // in the kernels of ec_kernels.hip; this file only builds tables and drives.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -26,6 +27,19 @@ constexpr double kDepTol = 1e-10;   // SPE default: drop a solution whose new di
 constexpr int64_t kAlign = 256;
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// A roctx range over one phase of host work (enqueue of a step, a solve's
+// start vector, its PCG, the update, the pushes).  rocprofv3 --marker-trace
+// records them nested, on the host clock; the kernels a range enqueues run
+// later on the stream, so the kernel trace gives their GPU time.  Without a
+// profiler attached a push/pop pair is a call through an empty dispatch
+// table.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 }  // namespace
 
@@ -1248,16 +1262,26 @@ static int32_t do_solve(ec_problem *h, int seq, int method, int window, int kmax
                         ec_solve_info *info, bool push)
 {
     int mode = 0;
-    int32_t rc = solve_prepare(h, seq, method, window, kmax, eps, b, bscale, x, o, info, &mode);
+    int32_t rc;
+    {
+        Range r("start vector");
+        rc = solve_prepare(h, seq, method, window, kmax, eps, b, bscale, x, o, info, &mode);
+    }
     if (rc) return rc;
-    if (o->precision == EC_PREC_FP64) {
-        rc = run_cg64(h, seq, mode, b, bscale, x, o, info);
-    } else {
-        if (mode == START_ZERO) fill(x, 0.0, h->npad, h->st);
-        rc = run_refined(h, seq, b, bscale, x, o, info);
+    {
+        Range r("pcg");
+        if (o->precision == EC_PREC_FP64) {
+            rc = run_cg64(h, seq, mode, b, bscale, x, o, info);
+        } else {
+            if (mode == START_ZERO) fill(x, 0.0, h->npad, h->st);
+            rc = run_refined(h, seq, b, bscale, x, o, info);
+        }
     }
     if (rc != EC_OK) return rc;
-    if (push && (method == EC_SV_SPE || method == EC_SV_POD)) seq_push(h, seq, method, x);
+    if (push && (method == EC_SV_SPE || method == EC_SV_POD)) {
+        Range r("push");
+        seq_push(h, seq, method, x);
+    }
     return launch_check(h, "solve");
 }
 
@@ -1696,6 +1720,7 @@ extern "C" int32_t ec_mass_solve(ec_handle h, const double *g, double *y, ec_sol
     if (!aligned(g) || !aligned(y))
         return fail(h, EC_ERR_ARG, "g, y must be 16-byte aligned device pointers");
     if (!h->nc) return fail(h, EC_ERR_ARG, "no conducting edges");
+    Range range("mass solve");
     gather_c(h->cslot_d, h->nc, g, h->m_g, h->st);
     int32_t rc = mass_solve(h, h->m_g, h->m_y, dev_info);
     if (rc) return rc;
@@ -1728,10 +1753,12 @@ extern "C" int32_t ec_mass_counters(ec_handle h, int64_t *solves, int64_t *iters
 static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const ec_step_opts *o,
                          ec_solve_info *info, bool split = false)
 {
+    Range step_range("step");
     hipStream_t st = h->st, sd = h->side;
     const int meth = o->start_method;
     split = split && (meth == EC_SV_SPE || meth == EC_SV_POD);
     if (split) {
+        Range r("push");
         const int seq = EC_SEQ_CPL;
         const double *x = h->sc;
         HIP_TRY(h, hipEventRecord(h->sev[0], st));
@@ -1741,10 +1768,15 @@ static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const e
     }
     step_begin(h->ctrl_d, m, h->wf, h->amp, h->freq, h->tau, h->ramp, dt, st, h->adapt_lam,
                h->adapt_safety);
-    int32_t rc = do_solve(h, EC_SEQ_SRC, meth, o->window, o->pod_kmax, o->pod_eps, h->xs_d,
-                          &h->ctrl_d->scale, h->sj, &o->solve, info, false);
+    int32_t rc;
+    {
+        Range r("source solve");
+        rc = do_solve(h, EC_SEQ_SRC, meth, o->window, o->pod_kmax, o->pod_eps, h->xs_d,
+                      &h->ctrl_d->scale, h->sj, &o->solve, info, false);
+    }
     if (rc) return rc;
     if (split) {
+        Range r("push");
         const int seq = EC_SEQ_SRC;
         const double *x = h->sj;
         HIP_TRY(h, hipEventRecord(h->sev[2], st));
@@ -1752,36 +1784,46 @@ static int32_t step_impl(ec_problem *h, int64_t m, double dt, double *A, const e
         seq_push_n(h, 1, &seq, meth, &x, sd, 1);
         HIP_TRY(h, hipEventRecord(h->sev[3], sd));
     }
-    UpdArgs u{};
-    u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
-    u.nc = h->nc; u.A = A; u.sj = h->sj; u.sc = h->sc; u.out = h->ac; u.dt = dt; u.apply = 0;
-    u.ctrl = h->ctrl_d;
-    if (h->mass_kind == EC_MASS_CONSISTENT && h->nc) {
-        // eq. 6 with a consistent M_c: g on C, M_c y = g (its own sequence),
-        // a_c^m = a_c^{m-1} - dt y
-        u.gout = h->m_g;
-        update_c(u, st);
-        rc = mass_solve(h, h->m_g, h->m_y, nullptr);
-        if (rc) return rc;
-        mass_axpy(h->cslot_d, h->nc, A, h->m_y, h->ctrl_d, h->ac, st);
-    } else {
-        update_c(u, st);
+    {
+        Range r("update");
+        UpdArgs u{};
+        u.g = h->g; u.m = h->mats_d; u.cmat = h->cmat_d; u.cslot = h->cslot_d; u.minv = h->minv_d;
+        u.nc = h->nc; u.A = A; u.sj = h->sj; u.sc = h->sc; u.out = h->ac; u.dt = dt; u.apply = 0;
+        u.ctrl = h->ctrl_d;
+        if (h->mass_kind == EC_MASS_CONSISTENT && h->nc) {
+            // eq. 6 with a consistent M_c: g on C, M_c y = g (its own sequence),
+            // a_c^m = a_c^{m-1} - dt y
+            u.gout = h->m_g;
+            update_c(u, st);
+            rc = mass_solve(h, h->m_g, h->m_y, nullptr);
+            if (rc) return rc;
+            mass_axpy(h->cslot_d, h->nc, A, h->m_y, h->ctrl_d, h->ac, st);
+        } else {
+            update_c(u, st);
+        }
+        if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
     }
-    if (h->has_cond) spmv(h->g, h->ac, h->bcpl, h->band_lo, h->band_hi, st);
     if (split) HIP_TRY(h, hipStreamWaitEvent(st, h->sev[1], 0));
-    rc = do_solve(h, EC_SEQ_CPL, meth, o->window, o->pod_kmax, o->pod_eps, h->bcpl, nullptr, h->sc,
-                  &o->solve, info ? info + 1 : nullptr, false);
+    {
+        Range r("coupling solve");
+        rc = do_solve(h, EC_SEQ_CPL, meth, o->window, o->pod_kmax, o->pod_eps, h->bcpl, nullptr,
+                      h->sc, &o->solve, info ? info + 1 : nullptr, false);
+    }
     if (rc) return rc;
     if (split) {
         HIP_TRY(h, hipStreamWaitEvent(st, h->sev[3], 0));
     } else if (meth == EC_SV_SPE || meth == EC_SV_POD) {
+        Range r("push");
         // both histories grow in the same launches: the source history is
         // next read by the source solve of the following step
         const int seqs[2] = {EC_SEQ_SRC, EC_SEQ_CPL};
         const double *xs[2] = {h->sj, h->sc};
         seq_push_n(h, 2, seqs, meth, xs, st);
     }
-    finish_state(h->g, A, h->ac, h->sj, h->sc, h->ctrl_d, 1, st);
+    {
+        Range r("finish state");
+        finish_state(h->g, A, h->ac, h->sj, h->sc, h->ctrl_d, 1, st);
+    }
     return launch_check(h, "step");
 }
 
@@ -1834,6 +1876,7 @@ extern "C" int32_t ec_set_state(ec_handle h, const double *A, const ec_solve_opt
     NEED_BOUND(h);
     flush_pending(h);
     if (!aligned(A) || !opts) return fail(h, EC_ERR_ARG, "A must be aligned; opts required");
+    Range range("set state");
     return set_state_impl(h, A, opts);
 }
 
@@ -1911,6 +1954,7 @@ extern "C" int32_t ec_cfl(ec_handle h, const double *A, int32_t power_iters, dou
     if (!aligned(A) || !lambda_max || power_iters < 1 || !(rtol > 0))
         return fail(h, EC_ERR_ARG, "bad arguments");
     if (h->nc == 0) return fail(h, EC_ERR_ARG, "no conducting edges");
+    Range range("cfl power method");
     hipStream_t st = h->st;
     std::vector<double> v(h->nc), gv(h->nc);
     uint32_t s = 12345u;
@@ -1999,6 +2043,7 @@ extern "C" int32_t ec_implicit_step(ec_handle h, int64_t m, double dt, double *A
                                     const ec_implicit_opts *o, ec_implicit_info *info)
 {
     NEED_BOUND(h);
+    Range range("implicit step");
     flush_pending(h);
     if (!aligned(A) || !o || !(dt > 0) || !std::isfinite(dt))
         return fail(h, EC_ERR_ARG, "need an aligned A, opts and dt > 0");
@@ -2412,6 +2457,7 @@ extern "C" int32_t ec_adjoint_forward(ec_handle h, int64_t n_steps, double dt,
                                       void *adj_ws, int64_t adj_bytes, double *A, double *loss)
 {
     NEED_BOUND(h);
+    Range range("adjoint forward");
     flush_pending(h);
     AdjWs w;
     int32_t rc = adj_args(h, n_steps, dt, checkpoint_every, opts, adj_ws, adj_bytes, A, &w);
@@ -2455,6 +2501,7 @@ extern "C" int32_t ec_adjoint_backward(ec_handle h, int64_t n_steps, double dt,
                                        double *grads)
 {
     NEED_BOUND(h);
+    Range range("adjoint backward");
     flush_pending(h);
     AdjWs w;
     int32_t rc = adj_args(h, n_steps, dt, checkpoint_every, opts, adj_ws, adj_bytes, nullptr, &w);
@@ -2875,13 +2922,26 @@ static int32_t batch_step_impl(ec_batch_s *b, int64_t m, const double *dt, doubl
     (void)A;
     const int n = (int)b->inst.size();
     step_begin_tab(b->step_tab, n, m, b->st);
-    int32_t rc = batch_solve(b, 0, o);
+    int32_t rc;
+    {
+        Range r("source solve");
+        rc = batch_solve(b, 0, o);
+    }
     if (rc) return rc;
-    update_c_tab(b->upd_tab, n, b->nc_max, b->st);
-    spmv_box_tab(b->box_tab, n, b->box_tpx, b->st);
-    rc = batch_solve(b, 1, o);
+    {
+        Range r("update");
+        update_c_tab(b->upd_tab, n, b->nc_max, b->st);
+        spmv_box_tab(b->box_tab, n, b->box_tpx, b->st);
+    }
+    {
+        Range r("coupling solve");
+        rc = batch_solve(b, 1, o);
+    }
     if (rc) return rc;
-    finish_state_tab(b->fin_tab, n, b->npad_max, b->st);
+    {
+        Range r("finish state");
+        finish_state_tab(b->fin_tab, n, b->npad_max, b->st);
+    }
     return launch_check(b->inst[0], "batch step");
 }
 
@@ -2967,6 +3027,7 @@ extern "C" int32_t ec_batch_set_tiles(ec_batch b, int32_t tiles_per_block)
 extern "C" int32_t ec_batch_step(ec_batch b, int64_t m, const double *dt, double *const *A,
                                  const ec_step_opts *opts)
 {
+    Range range("batch step");
     int32_t rc = batch_check(b, dt, A, opts);
     if (rc) return rc;
     rc = batch_tables(b, opts, dt, A);
@@ -3186,6 +3247,7 @@ extern "C" int32_t ec_graph_launch(void *graph_exec, void *hip_stream)
 {
     if (!graph_exec) return fail(nullptr, EC_ERR_ARG, "graph_exec is NULL");
     GraphBox *g = (GraphBox *)graph_exec;
+    Range range("graph launch");
     hipError_t e = hipGraphLaunch(g->ex, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
     if (g->h) g->h->pending_meth = g->meth;

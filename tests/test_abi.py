@@ -37,6 +37,21 @@ def test_header_symbols_exported(L):
     assert set(syms) == set(_lib.SIGNATURES), "binding signatures out of sync with ec.h"
 
 
+def test_roctx_phase_ranges_linked(L):
+    """The library marks its host phases (step, solves, start vector, PCG,
+    update, pushes) as roctx ranges: it imports the push/pop pair from the
+    roctx library rather than carrying its own stubs."""
+    import shutil
+    import subprocess
+    from paper_1611_06721_amd import _lib
+    nm = shutil.which("nm")
+    if not nm:
+        pytest.skip("nm not installed")
+    out = subprocess.run([nm, "-D", "--undefined-only", _lib.LIB_PATH], check=True,
+                         capture_output=True, text=True).stdout
+    assert re.search(r"\bU roctxRangePushA\b", out) and re.search(r"\bU roctxRangePop\b", out)
+
+
 def _create(L, wl):
     from paper_1611_06721_amd import _lib as E
     grid = E.Grid((C.c_int32 * 3)(*wl.n), (C.c_double * 3)(*wl.length))

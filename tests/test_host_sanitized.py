@@ -29,7 +29,7 @@ def test_abi_checks_under_host_asan_ubsan(tmp_path):
                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-shared-libsan"]
     cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
            "-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           *host_san, "-I", os.path.join(ROOT, "include"), "-I", csrc, "-o", lib, *srcs]
+           *host_san, "-I", os.path.join(ROOT, "include"), "-I", csrc, "-o", lib, *srcs, "-lrocprofiler-sdk-roctx"]
     subprocess.run(cmd, check=True, capture_output=True)
     child = ("import sys; from paper_1611_06721_amd import _lib; _lib.LIB_PATH = %r; "
              "import pytest; sys.exit(pytest.main(['-q', '-p', 'no:cacheprovider', "
