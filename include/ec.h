@@ -140,7 +140,7 @@ typedef struct {
      * and in the worst-status counter.  Eager calls ignore these. */
     int32_t graph_iters[2];
     /* 1: a captured step runs as one chain of kernels.  0 (default): with an
-     * SPE or POD history and FP64 solves, the history pushes run on a forked
+     * SPE history and FP64 solves, the history pushes run on a forked
      * branch beside the other sequence's work (see ec_graph_capture_step);
      * a chain suits many different graphs launched in turn.  Eager calls
      * ignore it. */
@@ -487,8 +487,9 @@ int32_t ec_batch_autotune(ec_batch b, const char *cache_path, int32_t *tiles_per
 
 /* HIP graph of one step (device step counter, fixed dt and opts) captured on
  * the bound stream; launch replays it on `hip_stream` (the bound stream).
- * With an SPE or POD history, FP64 solves and opts->graph_serial = 0 the
- * graph forks: the history pushes run on a
+ * With an SPE history, FP64 solves and opts->graph_serial = 0 the graph
+ * forks (POD steps, measured slower forked, are captured as one chain; so
+ * are FP32-refined solves): the history pushes run on a
  * side stream of the library beside the other sequence's work (the previous
  * step's coupling push beside the source start and solve, the source push
  * beside the coupling start and solve), so a launch leaves its own coupling

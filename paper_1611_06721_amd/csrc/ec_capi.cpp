@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -612,6 +613,44 @@ static double kn_diag_max(const ec_problem *h)
     return 1.0 / std::min(h->g.dinv[0], std::min(h->g.dinv[1], h->g.dinv[2]));
 }
 
+// The first dispatch of a kernel with a private segment on a hardware queue
+// makes the runtime set up that queue's scratch, with the queue idle for
+// about 0.13 ms (twice when a larger segment follows).  The branches of a
+// captured step run on queues the library's streams need not have used
+// eagerly, so the first replay of the first captured step of a process paid
+// it (two PCG kernels have small private segments).  Once per device, a
+// dispatch with a larger segment than any library kernel on a fresh stream
+// per hardware queue (HIP assigns streams to its GPU_MAX_HW_QUEUES queues in
+// turn, 4 by default) sets every queue up at bind.
+static int32_t warm_queue_scratch(ec_problem *h)
+{
+    static bool warmed[64] = {};
+    int dev = 0;
+    HIP_TRY(h, hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64 || warmed[dev]) return EC_OK;
+    int nq = 4;
+    if (const char *e = std::getenv("GPU_MAX_HW_QUEUES")) nq = std::atoi(e);
+    nq = std::min(std::max(nq, 1), 32);
+    std::vector<hipStream_t> ss(nq, nullptr);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < nq && e == hipSuccess; ++q) {
+        e = hipStreamCreateWithFlags(&ss[q], hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            scratch_warm(ss[q]);
+            e = hipGetLastError();
+        }
+    }
+    for (hipStream_t s : ss) {
+        if (!s) continue;
+        hipError_t e2 = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = e2;
+        (void)hipStreamDestroy(s);
+    }
+    if (e != hipSuccess) return fail(h, EC_ERR_HIP, "queue scratch set-up: %s", hipGetErrorString(e));
+    warmed[dev] = true;
+    return EC_OK;
+}
+
 extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64_t bytes,
                            int32_t window_cap)
 {
@@ -670,6 +709,10 @@ extern "C" int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64
     for (hipEvent_t &e : h->sev)
         if (!e) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (!h->side) HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    {
+        int rc = warm_queue_scratch(h);
+        if (rc) return rc;
+    }
     h->pending_meth = -1;
     h->cfl_lam = 0.0;
     h->tiles = (int)((h->S + kTile - 1) / kTile);
@@ -3077,6 +3120,11 @@ extern "C" int32_t ec_batch_graph_capture(ec_batch b, const double *dt, double *
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(nullptr, EC_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+    e = hipGraphUpload(ex, b->st);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ex);
+        return fail(nullptr, EC_ERR_HIP, "graph upload: %s", hipGetErrorString(e));
+    }
     *graph_exec = (void *)new GraphBox{ex, nullptr, -1};
     return EC_OK;
 }
@@ -3212,6 +3260,8 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     if (opts->graph_iters[0] < 0 || opts->graph_iters[1] < 0)
         return fail(h, EC_ERR_ARG, "graph_iters must be >= 0");
     flush_pending(h);
+    const bool fork = !opts->graph_serial && opts->solve.precision == EC_PREC_FP64 &&
+                      opts->start_method == EC_SV_SPE;
     // configure the histories eagerly so that no reset is recorded
     for (int s : {EC_SEQ_SRC, EC_SEQ_CPL}) {
         seq_ensure(h, s, opts->start_method, opts->window, opts->pod_kmax, opts->pod_eps);
@@ -3222,9 +3272,11 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     HIP_TRY(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
     h->graph_iters[EC_SEQ_SRC] = opts->graph_iters[0];
     h->graph_iters[EC_SEQ_CPL] = opts->graph_iters[1];
-    // the pushes on a branch of their own, except for a chain on request or
-    // FP32-refined solves (measured slower forked)
-    const bool fork = !opts->graph_serial && opts->solve.precision == EC_PREC_FP64;
+    // the pushes on a branch of their own (`fork` above: SPE histories and
+    // FP64 solves), except for a chain on request; FP32-refined solves and
+    // POD histories measured slower forked (a forked step pushes each
+    // sequence in launches of its own, and POD's pushes do not hide beside
+    // its one-block eigen-solves)
     rc = step_impl(h, -1, dt, A, opts, dev_info, fork);
     h->graph_iters[EC_SEQ_SRC] = h->graph_iters[EC_SEQ_CPL] = 0;
     hipError_t e = hipStreamEndCapture(h->st, &graph);
@@ -3237,8 +3289,14 @@ extern "C" int32_t ec_graph_capture_step(ec_handle h, double dt, double *A,
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(h, EC_ERR_HIP, "instantiate: %s", hipGetErrorString(e));
+    // upload now, so that the first launch does not pay for it
+    e = hipGraphUpload(ex, h->st);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ex);
+        return fail(h, EC_ERR_HIP, "graph upload: %s", hipGetErrorString(e));
+    }
     const int meth = opts->start_method;
-    const bool due = fork && (meth == EC_SV_SPE || meth == EC_SV_POD);
+    const bool due = fork;   // forked: this launch leaves its coupling push due
     *graph_exec = (void *)new GraphBox{ex, due ? h : nullptr, meth};
     return EC_OK;
 }

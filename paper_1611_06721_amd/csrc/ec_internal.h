@@ -369,6 +369,9 @@ struct StepArgs {
 };
 void step_begin_tab(const StepArgs *tab, int n, int64_t m, hipStream_t st);
 void fill(double *y, double v, int64_t n, hipStream_t st);
+// a kernel with a larger private segment than any other, touching no
+// global memory (sets up a hardware queue's scratch)
+void scratch_warm(hipStream_t st);
 void copy_c(const int *cslot, int nc, const double *src, double *dst, hipStream_t st);
 void mask_copy(const Geo &g, const double *x, double *y, int cls_keep, hipStream_t st);
 // FP32-refined solve: r = b - K_n x in FP64 (and r32 = r) with block

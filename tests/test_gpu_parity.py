@@ -405,7 +405,7 @@ def test_graph_replay_equals_eager(ec, oracle_mod, name, method):
         n_ref = int(its[20:].sum())
         assert np.array_equal(got, ref), budget
         assert c["iters_src"] + c["iters_cpl"] == n_ref
-        # a replay leaves its coupling solution due for a push (made beside
+        # a forked (SPE) replay leaves its coupling solution due for a push (made beside
         # the next step's source solve); eager steps after replays make it
         # first, so the run continues as the eager one
         G2.run(A2, 30, 5, dt, opts)
