@@ -165,7 +165,11 @@ int32_t ec_sizes(ec_handle h, int32_t window_cap, int64_t *n_padded, int64_t *n_
 
 /* Bind a HIP stream and a caller-owned device workspace of at least
  * ec_sizes(...) bytes (256-byte aligned).  Uploads the tables and zeroes the
- * state (a = 0, empty histories); synchronises the stream. */
+ * state (a = 0, empty histories); synchronises the stream.  The first bind on
+ * a device also sets up the scratch of every HIP hardware queue (one stream
+ * per queue, created, used by one kernel that touches no global memory, and
+ * destroyed), so that no replay of a captured step waits for it.  Returns
+ * EC_ERR_HIP if a HIP call fails. */
 int32_t ec_bind(ec_handle h, void *hip_stream, void *workspace, int64_t bytes,
                 int32_t window_cap);
 
