@@ -618,7 +618,8 @@ static double kn_diag_max(const ec_problem *h)
 // about 0.13 ms (twice when a larger segment follows).  The branches of a
 // captured step run on queues the library's streams need not have used
 // eagerly, so the first replay of the first captured step of a process paid
-// it (two PCG kernels have small private segments).  Once per device, a
+// it (the PCG iteration and the SPE start's dense step have small private
+// segments, from spill frames).  Once per device, a
 // dispatch with a larger segment than any library kernel on a fresh stream
 // per hardware queue (HIP assigns streams to its GPU_MAX_HW_QUEUES queues in
 // turn, 4 by default) sets every queue up at bind.
